@@ -1,0 +1,135 @@
+/*
+ * libgabor -- 2-D complex Gabor filter bank by kernel decomposition, and the
+ * Gaussian-windowed 2-D localized sliding DFT, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Um, Kim & Min, "Fast 2-D Complex Gabor Filter with Kernel
+ * Decomposition" (arXiv 1704.05231).  The bank output of Eq. (1)-(2) is
+ * computed as a horizontal 1-D Gabor pass J (Eq. (3)) followed by a vertical
+ * 1-D Gabor pass (Eq. (4)); the horizontal result of orientation theta is
+ * reused, conjugated, for pi - theta (Eq. (13)-(16)); Algorithm 1 is the bank
+ * schedule.  The localized SDFT is Eq. (17)-(18) computed the same way
+ * (Eq. (19)-(26), Algorithm 2).
+ *
+ * Conventions shared by every entry point:
+ *   - Images are single-channel FP32, row-major, H rows by W columns, with a
+ *     row stride in elements (>= W).  x is the column, y the row, 0-based.
+ *   - Outputs are complex64, interleaved (re, im) pairs of float, dense
+ *     row-major planes of H x W complex values, fully overwritten.
+ *   - All image and output pointers are DEVICE pointers owned by the caller;
+ *     input and output must not overlap.  Host arrays (omega, sigma, theta)
+ *     are read during the call only.
+ *   - Eq. (1) is a convolution: the kernel is evaluated at (x-k, y-l), so an
+ *     impulse reproduces the kernel itself.
+ *   - The Gaussian factor S (G(x,y) = S(x) S(y), Sec. II) is sampled at
+ *     integer offsets |t| <= R with R = floor(radius_sigmas * sigma + 0.5),
+ *     and normalised to unit sum over those taps (the paper fixes neither
+ *     the support nor the normalisation; this is the exact FIR the paper
+ *     calls lossless in Sec. IV-B).
+ *   - Every call is asynchronous on the given HIP stream (hipStream_t passed
+ *     as void*; NULL = the default stream).  Argument checks run on the host
+ *     before anything is enqueued; a rejected call writes nothing.  Device
+ *     faults surface at the caller's next synchronisation of the stream.
+ *   - No call throws; every call returns a gabor_status.
+ */
+#ifndef LIBGABOR_H
+#define LIBGABOR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gabor_plan_s* gabor_plan;
+
+typedef enum gabor_status {
+    GABOR_OK = 0,
+    GABOR_ERR_INVALID_ARG = 1,   /* a null pointer, a size <= 0, sigma <= 0,
+                                    a non-finite parameter, stride < W, a bad
+                                    enum value, a plan/image size mismatch */
+    GABOR_ERR_OUT_OF_MEMORY = 2, /* device or host allocation failed */
+    GABOR_ERR_DEVICE = 3,        /* a HIP runtime call or launch failed */
+    GABOR_ERR_UNSUPPORTED = 4    /* valid arguments this build cannot run */
+} gabor_status;
+
+typedef enum gabor_boundary {
+    GABOR_BOUNDARY_ZERO = 0,   /* f = 0 outside the image */
+    GABOR_BOUNDARY_MIRROR = 1  /* whole-sample mirror f(-1) = f(1), folded
+                                  repeatedly with period 2(n-1); n = 1 gives a
+                                  constant extension */
+} gabor_boundary;
+
+typedef enum gabor_precision {
+    GABOR_PREC_FP32 = 0,        /* FP32 products, FP32 accumulation */
+    GABOR_PREC_BF16_SPLIT = 1,  /* matrix cores: operands split hi+lo in
+                                   bfloat16, three products, FP32 accumulation */
+    GABOR_PREC_FP16_SPLIT = 2,  /* as above with float16 operands */
+    GABOR_PREC_BF16 = 3,        /* matrix cores: one bfloat16 product */
+    GABOR_PREC_FP16 = 4         /* matrix cores: one float16 product */
+} gabor_precision;
+
+/* Human-readable name of a status code (static storage, never NULL). */
+const char* gabor_status_string(gabor_status status);
+
+/*
+ * gabor_bank_plan -- prepare the bank of Algorithm 1 (Sec. II-B) for images
+ * of height x width.
+ *
+ *   out            receives the plan handle (set to NULL on failure).
+ *   n_freq         O >= 1 frequencies; omega[O] in radians per pixel
+ *                  (omega = 2 pi / lambda, Eq. (2)); sigma[O] > 0 in pixels,
+ *                  one Gaussian scale per frequency (the set Sigma of
+ *                  Algorithm 1).
+ *   n_orient       N >= 1 orientations; theta[N] in radians, or NULL for
+ *                  theta_k = k pi / N, k = 0..N-1 (Sec. II-B).  Orientations
+ *                  whose sum is pi share one horizontal pass (Eq. (13));
+ *                  unpaired orientations are computed on their own.
+ *   radius_sigmas  truncation of S in units of sigma (3.0 gives R = 3 sigma).
+ *   boundary       rule for samples outside the image.
+ *   precision      arithmetic of the Gaussian contractions.
+ *   hip_stream     stream used to upload the plan's tables.
+ *
+ * The plan owns device memory for its tap tables and any intermediate
+ * workspace; it is freed by gabor_bank_destroy.  One plan serves one stream
+ * at a time.
+ */
+gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t width,
+                             int32_t n_freq, const double* omega, const double* sigma,
+                             int32_t n_orient, const double* theta,
+                             double radius_sigmas, gabor_boundary boundary,
+                             gabor_precision precision, void* hip_stream);
+
+/*
+ * gabor_bank_apply -- run the bank on one image.
+ *
+ *   d_image           device FP32 image, height x width of the plan, row
+ *                     stride row_stride_elems (>= width).
+ *   d_out             device complex64 output, layout [O][N][H][W] (frequency
+ *                     major, then orientation in the order given to the
+ *                     plan), O*N*H*W*8 bytes, fully overwritten.
+ */
+gabor_status gabor_bank_apply(gabor_plan plan, const float* d_image,
+                              int64_t row_stride_elems, void* d_out, void* hip_stream);
+
+/* Release a plan and its device memory.  NULL is accepted (no-op). */
+gabor_status gabor_bank_destroy(gabor_plan plan);
+
+typedef struct gabor_plan_info {
+    int32_t height, width, n_freq, n_orient;
+    int32_t max_radius;          /* largest R over the frequencies */
+    int32_t n_row_passes;        /* horizontal passes per image (after reuse) */
+    int32_t n_col_passes;        /* vertical passes per image */
+    int32_t precision;           /* gabor_precision of the plan */
+    int64_t workspace_bytes;     /* device memory held by the plan */
+    int64_t real_macs;           /* real multiply-adds of one apply, counted as
+                                    K taps per real 1-D pass per pixel */
+} gabor_plan_info;
+
+/* Describe a plan (sizes, reuse, algorithmic work). */
+gabor_status gabor_bank_plan_info(gabor_plan plan, gabor_plan_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBGABOR_H */
