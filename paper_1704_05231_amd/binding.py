@@ -1,0 +1,185 @@
+"""ctypes binding of libgabor (include/libgabor.h).
+
+Argument marshalling only: every step of the filter runs in the HIP kernels
+of libgabor.so.  PyTorch supplies device memory (``data_ptr()``) and the
+current HIP stream.  There is no fallback: if libgabor.so is missing or no
+GPU is visible, calls raise.
+
+The functions keep the C names: ``gabor_bank_plan``, ``gabor_bank_apply``,
+``gabor_bank_destroy``, ``gabor_bank_plan_info``, ``gabor_status_string``.
+``GaborBank`` wraps a plan for torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgabor.so")
+
+GABOR_OK = 0
+STATUS = {0: "GABOR_OK", 1: "GABOR_ERR_INVALID_ARG", 2: "GABOR_ERR_OUT_OF_MEMORY",
+          3: "GABOR_ERR_DEVICE", 4: "GABOR_ERR_UNSUPPORTED"}
+BOUNDARY = {"zero": 0, "mirror": 1}
+PRECISION = {"fp32": 0, "bf16_split": 1, "fp16_split": 2, "bf16": 3, "fp16": 4}
+
+# Every symbol include/libgabor.h declares; the CPU tests check the exports.
+EXPORTS = ["gabor_status_string", "gabor_bank_plan", "gabor_bank_apply", "gabor_bank_destroy",
+           "gabor_bank_plan_info"]
+
+
+class GaborError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {STATUS.get(status, status)}")
+        self.status = status
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("n_freq", ctypes.c_int32), ("n_orient", ctypes.c_int32),
+                ("max_radius", ctypes.c_int32), ("n_row_passes", ctypes.c_int32),
+                ("n_col_passes", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_int64), ("real_macs", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load():
+    """Load libgabor.so (built in-tree by paper_1704_05231_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_1704_05231_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.gabor_status_string.argtypes = [ctypes.c_int]
+    lib.gabor_status_string.restype = ctypes.c_char_p
+    lib.gabor_bank_plan.argtypes = [ctypes.POINTER(P), i32, i32, i32, P, P, i32, P, f64,
+                                    ctypes.c_int, ctypes.c_int, P]
+    lib.gabor_bank_plan.restype = ctypes.c_int
+    lib.gabor_bank_apply.argtypes = [P, P, i64, P, P]
+    lib.gabor_bank_apply.restype = ctypes.c_int
+    lib.gabor_bank_destroy.argtypes = [P]
+    lib.gabor_bank_destroy.restype = ctypes.c_int
+    lib.gabor_bank_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
+    lib.gabor_bank_plan_info.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str):
+    if status != GABOR_OK:
+        raise GaborError(status, what)
+
+
+def _f64(a):
+    if a is None:
+        return None
+    return np.ascontiguousarray(np.atleast_1d(np.asarray(a, dtype=np.float64)))
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def gabor_status_string(status: int) -> str:
+    return load().gabor_status_string(int(status)).decode()
+
+
+def gabor_bank_plan(height, width, omega, sigma, n_orient, theta=None, radius_sigmas=3.0,
+                    boundary="zero", precision="fp32", stream=None) -> ctypes.c_void_p:
+    om, sg, th = _f64(omega), _f64(sigma), _f64(theta)
+    if om.shape != sg.shape:
+        raise ValueError("omega and sigma must have the same length")
+    if th is not None and th.size != n_orient:
+        raise ValueError("theta must have n_orient entries")
+    plan = ctypes.c_void_p()
+    st = load().gabor_bank_plan(ctypes.byref(plan), int(height), int(width), om.size, _p(om),
+                                _p(sg), int(n_orient), _p(th), float(radius_sigmas),
+                                BOUNDARY[boundary], PRECISION[precision], _stream(stream))
+    _check(st, "gabor_bank_plan")
+    return plan
+
+
+def gabor_bank_apply(plan, d_image: int, row_stride_elems: int, d_out: int, stream=None):
+    st = load().gabor_bank_apply(plan, ctypes.c_void_p(d_image), int(row_stride_elems),
+                                 ctypes.c_void_p(d_out), _stream(stream))
+    _check(st, "gabor_bank_apply")
+
+
+def gabor_bank_destroy(plan):
+    _check(load().gabor_bank_destroy(plan), "gabor_bank_destroy")
+
+
+def gabor_bank_plan_info(plan) -> PlanInfo:
+    info = PlanInfo()
+    _check(load().gabor_bank_plan_info(plan, ctypes.byref(info)), "gabor_bank_plan_info")
+    return info
+
+
+class GaborBank:
+    """A plan bound to one image size, for torch tensors on the GPU.
+
+    ``bank(img)`` takes a (H, W) float32 CUDA tensor (row stride may exceed W)
+    and returns a complex64 tensor [O, N, H, W] on the same device.
+    """
+
+    def __init__(self, height, width, omegas, sigmas, n_orient=None, thetas=None,
+                 radius_sigmas=3.0, boundary="zero", precision="fp32"):
+        if thetas is not None:
+            thetas = _f64(thetas)
+            n_orient = thetas.size if n_orient is None else n_orient
+        self.height, self.width = int(height), int(width)
+        self.n_freq = _f64(omegas).size
+        self.n_orient = int(n_orient)
+        self.precision = precision
+        self._plan = gabor_bank_plan(height, width, omegas, sigmas, self.n_orient, thetas,
+                                     radius_sigmas, boundary, precision)
+
+    @property
+    def info(self) -> PlanInfo:
+        return gabor_bank_plan_info(self._plan)
+
+    def __call__(self, img, out=None, stream=None):
+        import torch
+        if img.dtype != torch.float32 or img.dim() != 2 or not img.is_cuda:
+            raise ValueError("image must be a 2-D float32 GPU tensor")
+        if tuple(img.shape) != (self.height, self.width) or img.stride(1) != 1:
+            raise ValueError("image shape does not match the plan or is not row-major")
+        if out is None:
+            out = torch.empty((self.n_freq, self.n_orient, self.height, self.width),
+                              dtype=torch.complex64, device=img.device)
+        elif (out.dtype != torch.complex64 or not out.is_contiguous()
+              or tuple(out.shape) != (self.n_freq, self.n_orient, self.height, self.width)):
+            raise ValueError("out must be a contiguous complex64 [O, N, H, W] tensor")
+        gabor_bank_apply(self._plan, img.data_ptr(), img.stride(0), out.data_ptr(), stream)
+        return out
+
+    def close(self):
+        if self._plan:
+            gabor_bank_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def default_thetas(n: int) -> np.ndarray:
+    return np.array([math.pi * k / n for k in range(n)])

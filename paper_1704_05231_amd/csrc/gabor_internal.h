@@ -1,0 +1,53 @@
+// Internal declarations shared by the libgabor host code and its HIP kernels.
+// Nothing here is part of the public C ABI (include/libgabor.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gabor {
+
+// Tap blocks: every tap table is zero-padded to a multiple of this many taps.
+constexpr int kTapBlock = 4;
+
+// One vertical pass (Eq. (4)) over one horizontal result J.  It produces
+// F_a = J * k and, when out_b >= 0, F_b = conj(J) * k (the pi - theta
+// orientation, Eq. (15)-(16)), where k(t) = S(t) exp(i w sin(theta) t).
+struct ColJob {
+    int32_t freq;      // frequency index (selects R and the taps)
+    int32_t plane;     // J plane in the workspace
+    int32_t out_a;     // output channel index i*N + n
+    int32_t out_b;     // partner channel or -1
+    int32_t j_real;    // J is real (w cos(theta) == 0)
+    int32_t c_real;    // column taps are real (w sin(theta) == 0)
+    int32_t tap_off;   // offset of this job's [Kp][2] (c, d) taps in the tap table
+    int32_t pad_;
+};
+
+// Launch parameters of one horizontal-pass group: all horizontal passes of
+// one frequency that read the same image rows.
+struct RowGroup {
+    int32_t freq;
+    int32_t n_cplx;    // complex-J passes (taps c, d)
+    int32_t n_real;    // real-J passes (taps c only), 0 or 1
+    int32_t tap_off;   // offset of the [Kp][2*n_cplx + n_real] taps
+    int32_t plane0;    // first J plane; passes write plane0 .. plane0+n-1
+};
+
+struct FreqDesc {
+    int32_t R;         // truncation radius
+    int32_t K;         // 2R + 1
+    int32_t Kp;        // K padded to a multiple of kTapBlock
+};
+
+// Launchers (defined in gabor_fp32.hip).  They return the status of the
+// launch (hipGetLastError after enqueue).
+hipError_t launch_row_fp32(const float* img, int64_t stride, int H, int W, int boundary,
+                           const FreqDesc& fd, const RowGroup& g, const float* d_taps,
+                           float2* d_J, hipStream_t stream);
+
+hipError_t launch_col_fp32(const float2* d_J, int H, int W, int boundary, const FreqDesc& fd,
+                           const ColJob* d_jobs, int n_jobs, const float* d_taps,
+                           float2* d_out, hipStream_t stream);
+
+}  // namespace gabor

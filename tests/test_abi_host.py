@@ -1,0 +1,88 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/libgabor.h declares, and rejects bad arguments before
+any device work (a rejected call must not touch the GPU)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1704_05231_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "libgabor.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gabor_\w+|lsdft_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    declared = header_functions()
+    assert declared, "no functions parsed from the header"
+    for name in declared:
+        assert hasattr(lib, name), f"libgabor.so does not export {name}"
+    assert sorted(binding.EXPORTS) == declared
+
+
+def test_status_strings():
+    for code, name in binding.STATUS.items():
+        assert binding.gabor_status_string(code) == name
+    assert binding.gabor_status_string(99) == "GABOR_ERR_UNKNOWN"
+
+
+def _plan_raw(H=8, W=8, om=(1.0,), sg=(2.0,), N=4, th=None, rs=3.0, bnd=0, prec=0, out=True):
+    lib = binding.load()
+    om = np.asarray(om, np.float64)
+    sg = np.asarray(sg, np.float64)
+    th = None if th is None else np.asarray(th, np.float64)
+    plan = ctypes.c_void_p(1234)
+    ptr = ctypes.byref(plan) if out else None
+    st = lib.gabor_bank_plan(ptr, H, W, len(om), om.ctypes.data_as(ctypes.c_void_p),
+                             sg.ctypes.data_as(ctypes.c_void_p), N,
+                             None if th is None else th.ctypes.data_as(ctypes.c_void_p),
+                             rs, bnd, prec, None)
+    return st, plan
+
+
+@pytest.mark.parametrize("kw", [
+    dict(H=0), dict(W=-3), dict(N=0), dict(om=()), dict(sg=(0.0,)), dict(sg=(-1.0,)),
+    dict(sg=(float("inf"),)), dict(om=(float("nan"),)), dict(th=(0.0, float("inf"), 1.0, 2.0)),
+    dict(rs=-1.0), dict(rs=float("nan")), dict(bnd=7), dict(prec=9), dict(out=False),
+])
+def test_plan_rejects_bad_arguments(kw):
+    st, plan = _plan_raw(**kw)
+    assert st == 1
+    if kw.get("out", True):
+        assert plan.value is None     # the handle is cleared on failure
+
+
+def test_plan_rejects_null_parameter_arrays():
+    lib = binding.load()
+    plan = ctypes.c_void_p()
+    sg = np.array([1.0])
+    assert lib.gabor_bank_plan(ctypes.byref(plan), 4, 4, 1, None, sg.ctypes.data_as(ctypes.c_void_p),
+                               2, None, 3.0, 0, 0, None) == 1
+
+
+def test_apply_and_info_reject_null_plan():
+    lib = binding.load()
+    assert lib.gabor_bank_apply(None, ctypes.c_void_p(16), 8, ctypes.c_void_p(16), None) == 1
+    info = binding.PlanInfo()
+    assert lib.gabor_bank_plan_info(None, ctypes.byref(info)) == 1
+    assert lib.gabor_bank_destroy(None) == 0
+
+
+def test_forced_allocation_failure(monkeypatch):
+    monkeypatch.setenv("LIBGABOR_FAIL_ALLOC", "1")
+    st, plan = _plan_raw(om=(math.pi / 4, math.pi / 8), sg=(4.0, 4.0))
+    assert st == 2 and plan.value is None
+
+
+def test_oversized_radius_is_unsupported():
+    st, _ = _plan_raw(sg=(5000.0,))
+    assert st == 4
