@@ -123,10 +123,32 @@ typedef struct gabor_plan_info {
     int64_t workspace_bytes;     /* device memory held by the plan */
     int64_t real_macs;           /* real multiply-adds of one apply, counted as
                                     K taps per real 1-D pass per pixel */
+    int64_t row_real_macs;       /* ... of which in horizontal passes */
+    int64_t col_real_macs;       /* ... of which in vertical passes */
 } gabor_plan_info;
 
 /* Describe a plan (sizes, reuse, algorithmic work). */
 gabor_status gabor_bank_plan_info(gabor_plan plan, gabor_plan_info* info);
+
+/*
+ * Per-kernel timing (tracing hook; not part of the paper's method).
+ *
+ * gabor_profile_enable(plan, 1) clears the counters and makes every later
+ * apply on the plan bracket each kernel launch with a pair of HIP events
+ * recorded on the launch stream; gabor_profile_enable(plan, 0) stops it.
+ * gabor_profile_read waits for the recorded events, folds them into
+ * per-kernel totals and copies up to `capacity` entries into `stats`
+ * (n_stats receives the number of kernels seen).  Host pointers.
+ */
+typedef struct gabor_kernel_stat {
+    char name[32];       /* kernel name, e.g. "row_fp32" */
+    int64_t launches;    /* launches timed */
+    double total_ms;     /* sum of event-measured launch durations */
+} gabor_kernel_stat;
+
+gabor_status gabor_profile_enable(gabor_plan plan, int32_t enable);
+gabor_status gabor_profile_read(gabor_plan plan, gabor_kernel_stat* stats, int32_t capacity,
+                                int32_t* n_stats);
 
 #ifdef __cplusplus
 }

@@ -28,7 +28,7 @@ PRECISION = {"fp32": 0, "bf16_split": 1, "fp16_split": 2, "bf16": 3, "fp16": 4}
 
 # Every symbol include/libgabor.h declares; the CPU tests check the exports.
 EXPORTS = ["gabor_status_string", "gabor_bank_plan", "gabor_bank_apply", "gabor_bank_destroy",
-           "gabor_bank_plan_info"]
+           "gabor_bank_plan_info", "gabor_profile_enable", "gabor_profile_read"]
 
 
 class GaborError(RuntimeError):
@@ -42,7 +42,13 @@ class PlanInfo(ctypes.Structure):
                 ("n_freq", ctypes.c_int32), ("n_orient", ctypes.c_int32),
                 ("max_radius", ctypes.c_int32), ("n_row_passes", ctypes.c_int32),
                 ("n_col_passes", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("workspace_bytes", ctypes.c_int64), ("real_macs", ctypes.c_int64)]
+                ("workspace_bytes", ctypes.c_int64), ("real_macs", ctypes.c_int64),
+                ("row_real_macs", ctypes.c_int64), ("col_real_macs", ctypes.c_int64)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -68,6 +74,10 @@ def load():
     lib.gabor_bank_destroy.restype = ctypes.c_int
     lib.gabor_bank_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
     lib.gabor_bank_plan_info.restype = ctypes.c_int
+    lib.gabor_profile_enable.argtypes = [P, i32]
+    lib.gabor_profile_enable.restype = ctypes.c_int
+    lib.gabor_profile_read.argtypes = [P, ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
+    lib.gabor_profile_read.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -131,6 +141,20 @@ def gabor_bank_plan_info(plan) -> PlanInfo:
     return info
 
 
+def gabor_profile_enable(plan, enable: bool):
+    _check(load().gabor_profile_enable(plan, int(bool(enable))), "gabor_profile_enable")
+
+
+def gabor_profile_read(plan) -> dict:
+    """{kernel name: (launches, total_ms)} of the launches timed so far."""
+    cap = 16
+    arr = (KernelStat * cap)()
+    n = ctypes.c_int32()
+    _check(load().gabor_profile_read(plan, arr, cap, ctypes.byref(n)), "gabor_profile_read")
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms))
+            for i in range(min(n.value, cap))}
+
+
 class GaborBank:
     """A plan bound to one image size, for torch tensors on the GPU.
 
@@ -168,6 +192,12 @@ class GaborBank:
             raise ValueError("out must be a contiguous complex64 [O, N, H, W] tensor")
         gabor_bank_apply(self._plan, img.data_ptr(), img.stride(0), out.data_ptr(), stream)
         return out
+
+    def profile(self, enable: bool = True):
+        gabor_profile_enable(self._plan, enable)
+
+    def profile_read(self) -> dict:
+        return gabor_profile_read(self._plan)
 
     def close(self):
         if self._plan:

@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/libgabor.h"
@@ -31,11 +32,18 @@ struct gabor_plan_s {
     std::vector<ColJob> jobs;
     int32_t n_planes = 0;
     int32_t n_row_passes = 0, n_col_passes = 0;
-    int64_t real_macs = 0;
+    int64_t row_macs = 0, col_macs = 0;
     int64_t workspace_bytes = 0;
     float* d_taps = nullptr;
     ColJob* d_jobs = nullptr;
     float2* d_J = nullptr;
+    // per-kernel timing
+    bool prof = false;
+    struct Pending { int kind; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    std::vector<std::string> kind_names;
+    std::vector<gabor_kernel_stat> stats;
 };
 
 namespace {
@@ -71,11 +79,61 @@ void exact_cos_sin(double th, double* c, double* s)
 void release(gabor_plan p)
 {
     if (!p) return;
+    for (auto& q : p->pending) { (void)hipEventDestroy(q.a); (void)hipEventDestroy(q.b); }
+    for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
     if (p->d_taps) (void)hipFree(p->d_taps);
     if (p->d_jobs) (void)hipFree(p->d_jobs);
     if (p->d_J) (void)hipFree(p->d_J);
     delete p;
 }
+
+hipEvent_t take_event(gabor_plan p)
+{
+    if (!p->event_pool.empty()) {
+        hipEvent_t e = p->event_pool.back();
+        p->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int kind_index(gabor_plan p, const char* name)
+{
+    for (size_t i = 0; i < p->kind_names.size(); ++i)
+        if (p->kind_names[i] == name) return (int)i;
+    p->kind_names.push_back(name);
+    gabor_kernel_stat st{};
+    std::strncpy(st.name, name, sizeof(st.name) - 1);
+    p->stats.push_back(st);
+    return (int)p->kind_names.size() - 1;
+}
+
+// Brackets one launch with events when profiling is on.
+struct LaunchTimer {
+    gabor_plan p;
+    hipStream_t s;
+    int kind = -1;
+    hipEvent_t a = nullptr, b = nullptr;
+    LaunchTimer(gabor_plan plan, hipStream_t stream, const char* name) : p(plan), s(stream)
+    {
+        if (!p->prof) return;
+        kind = kind_index(p, name);
+        a = take_event(p);
+        b = take_event(p);
+        if (a && b && hipEventRecord(a, s) == hipSuccess) return;
+        if (a) p->event_pool.push_back(a);
+        if (b) p->event_pool.push_back(b);
+        a = b = nullptr;
+    }
+    ~LaunchTimer()
+    {
+        if (!a) return;
+        if (hipEventRecord(b, s) == hipSuccess) p->pending.push_back({kind, a, b});
+        else { p->event_pool.push_back(a); p->event_pool.push_back(b); }
+    }
+};
 
 struct RowPass {
     double wc;      // w cos(theta)
@@ -189,7 +247,7 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
                 taps.push_back((float)(s * std::sin(ws * t)));
             }
             const int convs = (jb.c_real ? 1 : 2) * (jb.j_real ? 1 : 2);
-            p->real_macs += (int64_t)convs * fd.K * npix;
+            p->col_macs += (int64_t)convs * fd.K * npix;
             p->n_col_passes += 1;
             (jb.j_real ? real : cplx).push_back(RowPass{wc, (bool)jb.j_real, (int)p->jobs.size()});
             p->jobs.push_back(jb);
@@ -224,7 +282,7 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
             for (size_t m = 0; m < members.size(); ++m) {
                 p->jobs[members[m]->job].plane = g.plane0 + (int)m;
                 const int convs = members[m]->real ? 1 : 2;
-                p->real_macs += (int64_t)convs * fd.K * npix;
+                p->row_macs += (int64_t)convs * fd.K * npix;
                 p->n_row_passes += 1;
             }
             p->n_planes += (int)members.size();
@@ -268,11 +326,13 @@ extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int
     if (row_stride_elems < p->W) return GABOR_ERR_INVALID_ARG;
     hipStream_t stream = (hipStream_t)hip_stream;
     for (const RowGroup& g : p->row_groups) {
+        LaunchTimer tm(p, stream, "row_fp32");
         if (launch_row_fp32(d_image, row_stride_elems, p->H, p->W, p->boundary, p->freqs[g.freq], g,
                             p->d_taps, p->d_J, stream) != hipSuccess)
             return GABOR_ERR_DEVICE;
     }
     for (int i = 0; i < p->O; ++i) {
+        LaunchTimer tm(p, stream, "col_fp32");
         if (launch_col_fp32(p->d_J, p->H, p->W, p->boundary, p->freqs[i], p->d_jobs + p->job_first[i],
                             p->job_count[i], p->d_taps, (float2*)d_out, stream) != hipSuccess)
             return GABOR_ERR_DEVICE;
@@ -284,6 +344,42 @@ extern "C" gabor_status gabor_bank_destroy(gabor_plan p)
 {
     release(p);
     return GABOR_OK;
+}
+
+extern "C" gabor_status gabor_profile_enable(gabor_plan p, int32_t enable)
+{
+    if (!p) return GABOR_ERR_INVALID_ARG;
+    for (auto& q : p->pending) {
+        (void)hipEventSynchronize(q.b);
+        p->event_pool.push_back(q.a);
+        p->event_pool.push_back(q.b);
+    }
+    p->pending.clear();
+    for (auto& st : p->stats) { st.launches = 0; st.total_ms = 0.0; }
+    p->prof = enable != 0;
+    return GABOR_OK;
+}
+
+extern "C" gabor_status gabor_profile_read(gabor_plan p, gabor_kernel_stat* stats, int32_t capacity,
+                                           int32_t* n_stats)
+{
+    if (!p || !n_stats || capacity < 0 || (capacity > 0 && !stats)) return GABOR_ERR_INVALID_ARG;
+    gabor_status rc = GABOR_OK;
+    for (auto& q : p->pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(q.b) != hipSuccess || hipEventElapsedTime(&ms, q.a, q.b) != hipSuccess)
+            rc = GABOR_ERR_DEVICE;
+        else {
+            p->stats[q.kind].launches += 1;
+            p->stats[q.kind].total_ms += ms;
+        }
+        p->event_pool.push_back(q.a);
+        p->event_pool.push_back(q.b);
+    }
+    p->pending.clear();
+    *n_stats = (int32_t)p->stats.size();
+    for (int32_t i = 0; i < capacity && i < (int32_t)p->stats.size(); ++i) stats[i] = p->stats[i];
+    return rc;
 }
 
 extern "C" gabor_status gabor_bank_plan_info(gabor_plan p, gabor_plan_info* info)
@@ -300,6 +396,8 @@ extern "C" gabor_status gabor_bank_plan_info(gabor_plan p, gabor_plan_info* info
     info->n_col_passes = p->n_col_passes;
     info->precision = p->precision;
     info->workspace_bytes = p->workspace_bytes;
-    info->real_macs = p->real_macs;
+    info->real_macs = p->row_macs + p->col_macs;
+    info->row_real_macs = p->row_macs;
+    info->col_real_macs = p->col_macs;
     return GABOR_OK;
 }
