@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgabor.so")
 
-SOURCES = ["gabor_plan.cpp", "gabor_fp32.hip"]
+SOURCES = ["gabor_plan.cpp", "gabor_fp32.hip", "gabor_fused.hip"]
 ARCH = "gfx950"
 
 

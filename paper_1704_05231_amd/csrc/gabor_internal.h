@@ -40,6 +40,41 @@ struct FreqDesc {
     int32_t Kp;        // K padded to a multiple of kTapBlock
 };
 
+// Fused streaming matrix-core kernel (gabor_fused.hip): one horizontal
+// result and its vertical pass per workgroup over a 64-column strip, J held
+// in an LDS ring.
+enum FusedOp { FUSED_F32 = 0, FUSED_BF16 = 1, FUSED_BF16X3 = 2, FUSED_F16 = 3, FUSED_F16X3 = 4 };
+constexpr int kStreamMaxQuarter = 32;   // contracted length L = 4Q <= 128: R <= 56
+
+struct FusedJob {
+    int32_t out_a;     // output channel i*N + n
+    int32_t out_b;     // pi - theta partner channel or -1
+    int32_t j_real;    // horizontal taps have no sine part (w cos(theta) == 0)
+    int32_t c_real;    // vertical taps have no sine part (w sin(theta) == 0)
+    int32_t tap_off;   // [4][L+16] zero-padded reversed taps: row c, row d, col c, col d
+    int32_t pad_[3];
+};
+
+struct StreamArgs {
+    const float* img;
+    int64_t stride;
+    int32_t H, W, boundary, R;
+    int32_t seg_rows;          // rows per strip segment (multiple of 16)
+    int32_t n_xs, n_ys, n_jobs;
+    const FusedJob* jobs;
+    const float* taps;
+    float2* out;
+    float in_scale;            // image scale before conversion (16-bit range)
+    float mid_scale;           // J scale after the horizontal pass
+    float out_scale;           // output scale after the vertical pass
+    float tap_scale[2];        // horizontal, vertical tap scales
+};
+
+int stream_quarter(int op, int R);             // Q for radius R (L = 4Q >= 16 + 2R)
+size_t stream_lds_bytes(int op, int Q);
+int stream_strip_width();
+hipError_t launch_stream(int op, const StreamArgs& a, int Q, hipStream_t stream);
+
 // Launchers (defined in gabor_fp32.hip).  They return the status of the
 // launch (hipGetLastError after enqueue).
 hipError_t launch_row_fp32(const float* img, int64_t stride, int H, int W, int boundary,

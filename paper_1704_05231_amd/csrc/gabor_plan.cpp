@@ -22,20 +22,39 @@
 
 using namespace gabor;
 
+namespace {
+// How one frequency is computed: the fused kernel (jobs in fjobs) or the
+// two-pass kernels (jobs in jobs, J planes written by the row groups).
+struct FreqLaunch {
+    bool fused;
+    int q;            // operand quarter: contracted length 4q (fused)
+    int seg_rows;     // strip segment rows (fused)
+    float in_scale, mid_scale, out_scale, tap_scale[2];
+    int first;        // first job
+    int count;        // jobs
+};
+const char* const kFusedNames[5] = {"stream_f32", "stream_bf16", "stream_bf16x3", "stream_f16", "stream_f16x3"};
+enum { ALGO_AUTO = 0, ALGO_TWOPASS = 1 };
+}  // namespace
+
 struct gabor_plan_s {
     int32_t H = 0, W = 0, O = 0, N = 0;
     int32_t boundary = 0;
     int32_t precision = 0;
     std::vector<FreqDesc> freqs;
     std::vector<RowGroup> row_groups;
-    std::vector<int32_t> job_first, job_count;   // per frequency, into jobs
-    std::vector<ColJob> jobs;
+    std::vector<ColJob> jobs;              // two-pass vertical jobs
+    std::vector<FusedJob> fjobs;           // fused jobs
+    std::vector<FreqLaunch> launches;      // per frequency
+    std::vector<int> order;                // launch order of the frequencies
+    int fused_op = FUSED_F32;
     int32_t n_planes = 0;
     int32_t n_row_passes = 0, n_col_passes = 0;
     int64_t row_macs = 0, col_macs = 0;
     int64_t workspace_bytes = 0;
     float* d_taps = nullptr;
     ColJob* d_jobs = nullptr;
+    FusedJob* d_fjobs = nullptr;
     float2* d_J = nullptr;
     // per-kernel timing
     bool prof = false;
@@ -83,6 +102,7 @@ void release(gabor_plan p)
     for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
     if (p->d_taps) (void)hipFree(p->d_taps);
     if (p->d_jobs) (void)hipFree(p->d_jobs);
+    if (p->d_fjobs) (void)hipFree(p->d_fjobs);
     if (p->d_J) (void)hipFree(p->d_J);
     delete p;
 }
@@ -181,7 +201,11 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
     if ((int64_t)height * width > (int64_t)INT32_MAX || height > 65535) return GABOR_ERR_UNSUPPORTED;
     for (int i = 0; i < n_freq; ++i)
         if (std::floor(radius_sigmas * sigma[i] + 0.5) > (double)kMaxRadius) return GABOR_ERR_UNSUPPORTED;
-    if (precision != GABOR_PREC_FP32) return GABOR_ERR_UNSUPPORTED;
+    // LIBGABOR_ALGO=twopass selects the FP32 vector-ALU two-pass kernels
+    // (comparison and testing); the default runs the fused kernel wherever
+    // the band fits it.
+    const char* algo_env = std::getenv("LIBGABOR_ALGO");
+    const int algo = (algo_env && std::strcmp(algo_env, "twopass") == 0) ? ALGO_TWOPASS : ALGO_AUTO;
 
     gabor_plan p = new (std::nothrow) gabor_plan_s;
     if (!p) return GABOR_ERR_OUT_OF_MEMORY;
@@ -191,6 +215,13 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
     p->N = n_orient;
     p->boundary = boundary;
     p->precision = precision;
+    switch (precision) {
+        case GABOR_PREC_FP32: p->fused_op = FUSED_F32; break;
+        case GABOR_PREC_BF16_SPLIT: p->fused_op = FUSED_BF16X3; break;
+        case GABOR_PREC_FP16_SPLIT: p->fused_op = FUSED_F16X3; break;
+        case GABOR_PREC_BF16: p->fused_op = FUSED_BF16; break;
+        case GABOR_PREC_FP16: p->fused_op = FUSED_F16; break;
+    }
 
     // Orientation geometry, shared by every frequency.
     std::vector<double> cs(n_orient), sn(n_orient);
@@ -216,10 +247,11 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
         }
         for (double& v : S) v /= sum;
 
-        // Pair orientations (Eq. (13)-(16)) and create the vertical jobs.
+        // Pair orientations (Eq. (13)-(16)): one vertical job per horizontal
+        // result, producing theta and, when present, pi - theta.
         std::vector<char> used(n_orient, 0);
-        std::vector<RowPass> cplx, real;
-        const int job0 = (int)p->jobs.size();
+        std::vector<ColJob> fjobs;
+        std::vector<double> fwc, fws;
         for (int n = 0; n < n_orient; ++n) {
             if (used[n]) continue;
             used[n] = 1;
@@ -238,22 +270,88 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
                         break;
                     }
             }
+            p->col_macs += (int64_t)((jb.c_real ? 1 : 2) * (jb.j_real ? 1 : 2)) * fd.K * npix;
+            p->row_macs += (int64_t)(jb.j_real ? 1 : 2) * fd.K * npix;
+            p->n_col_passes += 1;
+            p->n_row_passes += 1;
+            fjobs.push_back(jb);
+            fwc.push_back(wc);
+            fws.push_back(ws);
+        }
+
+        const int q = stream_quarter(p->fused_op, fd.R);
+        const bool fused = q <= kStreamMaxQuarter && algo != ALGO_TWOPASS;
+        if (!fused && precision != GABOR_PREC_FP32) {
+            release(p);
+            return GABOR_ERR_UNSUPPORTED;
+        }
+        FreqLaunch fl{};
+        fl.fused = fused;
+        fl.q = q;
+        fl.in_scale = fl.mid_scale = fl.out_scale = fl.tap_scale[0] = fl.tap_scale[1] = 1.0f;
+        if (fused) {
+            // Strip segments at least four times the lead-in, so that the
+            // lead-in recomputation stays under a quarter of the J rows.
+            const int L = 4 * q;
+            fl.seg_rows = std::max(128, 4 * L);
+            if (fl.seg_rows > height) fl.seg_rows = (height + 15) / 16 * 16;
+            if (p->fused_op == FUSED_F16 || p->fused_op == FUSED_F16X3) {
+                // float16 range: image scaled by 2^8 (|f| <= 128 stays below
+                // 2^15), taps by the power of two that brings S(0) to
+                // [2^13, 2^14); results scaled back exactly.
+                const int kt = 13 - (int)std::floor(std::log2(S[fd.R]));
+                const float ts = std::ldexp(1.0f, kt);
+                fl.in_scale = 256.0f;
+                fl.tap_scale[0] = fl.tap_scale[1] = ts;
+                fl.mid_scale = 1.0f / ts;
+                fl.out_scale = 1.0f / (256.0f * ts);
+            }
+            // Reversed taps krev[T] = k(R - T), zero-padded: entry m holds krev[m - 16].
+            const int KT = L + 16;
+            fl.first = (int)p->fjobs.size();
+            for (size_t j = 0; j < fjobs.size(); ++j) {
+                FusedJob f{};
+                f.out_a = fjobs[j].out_a;
+                f.out_b = fjobs[j].out_b;
+                f.j_real = fjobs[j].j_real;
+                f.c_real = fjobs[j].c_real;
+                f.tap_off = (int)taps.size();
+                const double w4[4] = {fwc[j], fwc[j], fws[j], fws[j]};
+                for (int set = 0; set < 4; ++set)
+                    for (int m = 0; m < KT; ++m) {
+                        const int T = m - 16;
+                        double v = 0.0;
+                        if (T >= 0 && T < fd.K) {
+                            const int t = fd.R - T;
+                            v = S[T] * ((set & 1) ? std::sin(w4[set] * t) : std::cos(w4[set] * t));
+                        }
+                        taps.push_back((float)v);
+                    }
+                p->fjobs.push_back(f);
+            }
+            fl.count = (int)fjobs.size();
+            p->launches.push_back(fl);
+            continue;
+        }
+
+        // Two-pass: vertical jobs read J planes written by horizontal groups.
+        fl.first = (int)p->jobs.size();
+        std::vector<RowPass> cplx, real;
+        for (size_t q = 0; q < fjobs.size(); ++q) {
+            ColJob jb = fjobs[q];
             // Column taps (reversed): c(R - T), d(R - T) with k(t) = S(t) e^{i ws t}.
             jb.tap_off = (int)taps.size();
             for (int T = 0; T < fd.Kp; ++T) {
                 const int t = fd.R - T;
                 const double s = T < fd.K ? S[T] : 0.0;   // S is symmetric: S(R-T) = S[T]
-                taps.push_back((float)(s * std::cos(ws * t)));
-                taps.push_back((float)(s * std::sin(ws * t)));
+                taps.push_back((float)(s * std::cos(fws[q] * t)));
+                taps.push_back((float)(s * std::sin(fws[q] * t)));
             }
-            const int convs = (jb.c_real ? 1 : 2) * (jb.j_real ? 1 : 2);
-            p->col_macs += (int64_t)convs * fd.K * npix;
-            p->n_col_passes += 1;
-            (jb.j_real ? real : cplx).push_back(RowPass{wc, (bool)jb.j_real, (int)p->jobs.size()});
+            (jb.j_real ? real : cplx).push_back(RowPass{fwc[q], (bool)jb.j_real, (int)p->jobs.size()});
             p->jobs.push_back(jb);
         }
-        p->job_first.push_back(job0);
-        p->job_count.push_back((int)p->jobs.size() - job0);
+        fl.count = (int)fjobs.size();
+        p->launches.push_back(fl);
 
         // Horizontal groups: up to 6 complex passes plus at most one real pass
         // share one staged image row.
@@ -265,7 +363,6 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
             g.n_real = ri < real.size() ? 1 : 0;
             g.plane0 = p->n_planes;
             g.tap_off = (int)taps.size();
-            const int NT = 2 * g.n_cplx + g.n_real;
             std::vector<const RowPass*> members;
             for (int c = 0; c < g.n_cplx; ++c) members.push_back(&cplx[ci + c]);
             if (g.n_real) members.push_back(&real[ri]);
@@ -278,13 +375,7 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
                 }
                 if (g.n_real) taps.push_back((float)s);
             }
-            (void)NT;
-            for (size_t m = 0; m < members.size(); ++m) {
-                p->jobs[members[m]->job].plane = g.plane0 + (int)m;
-                const int convs = members[m]->real ? 1 : 2;
-                p->row_macs += (int64_t)convs * fd.K * npix;
-                p->n_row_passes += 1;
-            }
+            for (size_t m = 0; m < members.size(); ++m) p->jobs[members[m]->job].plane = g.plane0 + (int)m;
             p->n_planes += (int)members.size();
             p->row_groups.push_back(g);
             ci += g.n_cplx;
@@ -292,25 +383,33 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
         }
     }
 
+    for (int i = 0; i < n_freq; ++i) p->order.push_back(i);
+    std::stable_sort(p->order.begin(), p->order.end(),
+                     [&](int a, int b) { return p->freqs[a].R > p->freqs[b].R; });
+
     // Device tables and workspace.
     const size_t taps_bytes = taps.size() * sizeof(float);
     const size_t jobs_bytes = p->jobs.size() * sizeof(ColJob);
+    const size_t fjobs_bytes = p->fjobs.size() * sizeof(FusedJob);
     const size_t J_bytes = (size_t)p->n_planes * (size_t)npix * sizeof(float2);
-    p->workspace_bytes = (int64_t)(taps_bytes + jobs_bytes + J_bytes);
+    p->workspace_bytes = (int64_t)(taps_bytes + jobs_bytes + fjobs_bytes + J_bytes);
     if (env_flag("LIBGABOR_FAIL_ALLOC")) {
         release(p);
         return GABOR_ERR_OUT_OF_MEMORY;
     }
     hipStream_t stream = (hipStream_t)hip_stream;
     hipError_t e;
-    if ((e = hipMalloc((void**)&p->d_taps, taps_bytes)) != hipSuccess ||
-        (e = hipMalloc((void**)&p->d_jobs, jobs_bytes)) != hipSuccess ||
-        (e = hipMalloc((void**)&p->d_J, J_bytes)) != hipSuccess) {
+    e = hipMalloc((void**)&p->d_taps, taps_bytes);
+    if (e == hipSuccess && jobs_bytes) e = hipMalloc((void**)&p->d_jobs, jobs_bytes);
+    if (e == hipSuccess && fjobs_bytes) e = hipMalloc((void**)&p->d_fjobs, fjobs_bytes);
+    if (e == hipSuccess && J_bytes) e = hipMalloc((void**)&p->d_J, J_bytes);
+    if (e != hipSuccess) {
         release(p);
         return e == hipErrorOutOfMemory ? GABOR_ERR_OUT_OF_MEMORY : GABOR_ERR_DEVICE;
     }
     if (hipMemcpyAsync(p->d_taps, taps.data(), taps_bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(p->d_jobs, p->jobs.data(), jobs_bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        (jobs_bytes && hipMemcpyAsync(p->d_jobs, p->jobs.data(), jobs_bytes, hipMemcpyHostToDevice, stream) != hipSuccess) ||
+        (fjobs_bytes && hipMemcpyAsync(p->d_fjobs, p->fjobs.data(), fjobs_bytes, hipMemcpyHostToDevice, stream) != hipSuccess) ||
         hipStreamSynchronize(stream) != hipSuccess) {
         release(p);
         return GABOR_ERR_DEVICE;
@@ -331,11 +430,37 @@ extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int
                             p->d_taps, p->d_J, stream) != hipSuccess)
             return GABOR_ERR_DEVICE;
     }
-    for (int i = 0; i < p->O; ++i) {
-        LaunchTimer tm(p, stream, "col_fp32");
-        if (launch_col_fp32(p->d_J, p->H, p->W, p->boundary, p->freqs[i], p->d_jobs + p->job_first[i],
-                            p->job_count[i], p->d_taps, (float2*)d_out, stream) != hipSuccess)
-            return GABOR_ERR_DEVICE;
+    // Heaviest frequencies (largest R) first.
+    for (int i : p->order) {
+        const FreqLaunch& fl = p->launches[i];
+        if (fl.fused) {
+            LaunchTimer tm(p, stream, kFusedNames[p->fused_op]);
+            StreamArgs sa{};
+            sa.img = d_image;
+            sa.stride = row_stride_elems;
+            sa.H = p->H;
+            sa.W = p->W;
+            sa.boundary = p->boundary;
+            sa.R = p->freqs[i].R;
+            sa.seg_rows = fl.seg_rows;
+            sa.n_xs = (p->W + stream_strip_width() - 1) / stream_strip_width();
+            sa.n_ys = (p->H + fl.seg_rows - 1) / fl.seg_rows;
+            sa.n_jobs = fl.count;
+            sa.jobs = p->d_fjobs + fl.first;
+            sa.taps = p->d_taps;
+            sa.out = (float2*)d_out;
+            sa.in_scale = fl.in_scale;
+            sa.mid_scale = fl.mid_scale;
+            sa.out_scale = fl.out_scale;
+            sa.tap_scale[0] = fl.tap_scale[0];
+            sa.tap_scale[1] = fl.tap_scale[1];
+            if (launch_stream(p->fused_op, sa, fl.q, stream) != hipSuccess) return GABOR_ERR_DEVICE;
+        } else {
+            LaunchTimer tm(p, stream, "col_fp32");
+            if (launch_col_fp32(p->d_J, p->H, p->W, p->boundary, p->freqs[i], p->d_jobs + fl.first,
+                                fl.count, p->d_taps, (float2*)d_out, stream) != hipSuccess)
+                return GABOR_ERR_DEVICE;
+        }
     }
     return GABOR_OK;
 }
