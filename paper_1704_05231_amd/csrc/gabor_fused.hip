@@ -47,9 +47,26 @@ constexpr int kThreads = 256;
 // Operand storage and matrix-core step for each arithmetic form.
 template <int OP> struct Form;
 
+// Wait until the last FP32 matrix-core result is written before any vector
+// instruction reads it.  The compiler schedules reads of a
+// v_mfma_f32_16x16x4_f32 result 10 wait states after the instruction, and on
+// gfx950 such reads of the last accumulator register returned stale values;
+// 16 wait states behind scheduling barriers remove the race.
+// The accumulators are asm operands kept in AGPRs, so no copy of them can
+// be placed before the wait.
+__device__ __forceinline__ void f32_mfma_drain(f4_t& x, f4_t& y)
+{
+    asm volatile("s_nop 7\n\ts_nop 7" : "+a"(x), "+a"(y));
+}
+__device__ __forceinline__ void f32_mfma_drain(f4_t& x, f4_t& y, f4_t& z, f4_t& u)
+{
+    asm volatile("s_nop 7\n\ts_nop 7" : "+a"(x), "+a"(y), "+a"(z), "+a"(u));
+}
+
 template <> struct Form<FUSED_F32> {
     using T = float;
     static constexpr bool split = false;
+    static constexpr bool drain = true;
     static constexpr int per_mma = 1;     // k values per lane per instruction
     static __device__ __forceinline__ void cvt(float x, T& hi, T& lo) { hi = x; lo = 0.0f; }
     template <int Q>
@@ -77,6 +94,7 @@ __device__ __forceinline__ f4_t mfma16(f4_t acc, Vec8<_Float16>::type a, Vec8<_F
 template <typename E, bool SPLIT> struct Form16 {
     using T = E;
     static constexpr bool split = SPLIT;
+    static constexpr bool drain = false;
     static constexpr int per_mma = 8;
     static __device__ __forceinline__ void cvt(float x, T& hi, T& lo)
     {
@@ -130,6 +148,26 @@ __device__ __forceinline__ int xcd_local_id(int b, int nb)
     return x * q + min(x, r) + b / 8;
 }
 
+// Workgroup barrier that orders LDS only: global loads and stores stay in
+// flight across it (a full __syncthreads would wait for the output stores).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Buffer resources: raw buffer loads past num_records return 0 and stores
+// past it are dropped, so edge handling needs no branch around a memory
+// instruction and the outstanding-access counts stay static.
+typedef int i2_t __attribute__((ext_vector_type(2)));
+constexpr uint32_t kOutside = 0xFFFFFFF0u;   // an offset past every resource
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
 // 16-byte LDS copies of Q consecutive operand values.
 template <typename T, int Q>
 __device__ __forceinline__ void lds_get(T* dst, const T* src)
@@ -140,8 +178,11 @@ __device__ __forceinline__ void lds_get(T* dst, const T* src)
     for (int p = 0; p < Q; p += per) *reinterpret_cast<float4*>(dst + p) = *reinterpret_cast<const float4*>(src + p);
 }
 
-template <int OP, int Q>
-__global__ __launch_bounds__(kThreads) void k_stream(StreamArgs a)
+// JR: J is real (horizontal taps have no sine part); CR: vertical taps have
+// no sine part.  Both are compile-time so that no branch separates a
+// matrix-core chain from the reads of its result.
+template <int OP, int Q, bool JR, bool CR>
+__device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob& jb, int job_rest)
 {
     using F = Form<OP>;
     using T = typename F::T;
@@ -154,23 +195,21 @@ __global__ __launch_bounds__(kThreads) void k_stream(StreamArgs a)
     constexpr int WP = WF + PAD;
     constexpr int NPL = SPLIT ? 2 : 1;       // hi (+ lo) copies
     constexpr int JPLANE = kSX * RP;         // one J component of one copy
-    constexpr int FBUF = 16 * WP;            // one slab of one copy
+    constexpr int FROWS = ((16 * WF + kThreads - 1) / kThreads * kThreads + WF - 1) / WF;
+    constexpr int FBUF = FROWS * WP;         // one slab of one copy (+ padding rows)
 
     extern __shared__ float4 stream_lds4[];
     T* Jst = reinterpret_cast<T*>(stream_lds4);             // [NPL][2 comps][kSX][RP]
     T* Fst = Jst + NPL * 2 * JPLANE;                         // [NPL][2 bufs][16][WP]
 
-    const int lid = xcd_local_id(blockIdx.x, gridDim.x);
-    const int job = lid % a.n_jobs;
-    const int rest = lid / a.n_jobs;
+    const int rest = job_rest;
     const int xs = rest % a.n_xs, ys = rest / a.n_xs;
-    const FusedJob jb = a.jobs[job];
     const int x0 = xs * kSX, yseg = ys * a.seg_rows;
     const int nsteps = (min(a.seg_rows, a.H - yseg) + 15) / 16;
     const int R = a.R;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int o = lane & 15, g = lane >> 4;
-    const bool jr = jb.j_real != 0, cr = jb.c_real != 0;
+    constexpr bool jr = JR, cr = CR;
     const float* tab = a.taps + jb.tap_off;                  // [4][L + 16]: row c, row d, col c, col d
     constexpr int KT = L + 16;
 
@@ -187,36 +226,34 @@ __global__ __launch_bounds__(kThreads) void k_stream(StreamArgs a)
     }
 
     // ---- image slab staging: rows yseg - R + 16 b + i, columns x0 - R + c
+    // (lanes past the slab read nothing and write the padding rows).
     constexpr int SLAB = 16 * WF;
     constexpr int PER_T = (SLAB + kThreads - 1) / kThreads;
-    float pre[PER_T];
-    auto slab_load = [&](int b) {
+    const __amdgpu_buffer_rsrc_t img_rsrc =
+        make_rsrc(a.img, (uint32_t)(((int64_t)(a.H - 1) * a.stride + a.W) * 4));
+    auto slab_load = [&](int b, float (&pre)[PER_T]) {
 #pragma unroll
         for (int k = 0; k < PER_T; ++k) {
             const int idx = tid + k * kThreads;
-            float v = 0.0f;
-            if (idx < SLAB) {
-                const int r = idx / WF, c = idx - r * WF;
-                const int yy = fold_index(yseg - R + 16 * b + r, a.H, a.boundary);
-                const int xx = fold_index(x0 - R + c, a.W, a.boundary);
-                if (yy >= 0 && xx >= 0) v = a.img[(int64_t)yy * a.stride + xx];
-            }
-            pre[k] = v * a.in_scale;
+            const int r = idx / WF, c = idx - r * WF;
+            const int yy = fold_index(yseg - R + 16 * b + r, a.H, a.boundary);
+            const int xx = fold_index(x0 - R + c, a.W, a.boundary);
+            const uint32_t off = (idx < SLAB && yy >= 0 && xx >= 0)
+                                     ? (uint32_t)(((int64_t)yy * a.stride + xx) * 4) : kOutside;
+            pre[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(img_rsrc, (int)off, 0, 0));
         }
     };
-    auto slab_store = [&](int b) {
+    auto slab_store = [&](int b, const float (&pre)[PER_T]) {
         T* hi = Fst + (b & 1) * FBUF;
         T* lo = hi + 2 * FBUF;
 #pragma unroll
         for (int k = 0; k < PER_T; ++k) {
             const int idx = tid + k * kThreads;
-            if (idx < SLAB) {
-                const int r = idx / WF, c = idx - r * WF;
-                T h, l;
-                F::cvt(pre[k], h, l);
-                hi[r * WP + c] = h;
-                if (SPLIT) lo[r * WP + c] = l;
-            }
+            const int r = idx / WF, c = idx - r * WF;
+            T h, l;
+            F::cvt(pre[k] * a.in_scale, h, l);
+            hi[r * WP + c] = h;
+            if (SPLIT) lo[r * WP + c] = l;
         }
     };
 
@@ -229,7 +266,8 @@ __global__ __launch_bounds__(kThreads) void k_stream(StreamArgs a)
         if (SPLIT) lds_get<T, Q>(al, fl);
         f4_t re = {0.f, 0.f, 0.f, 0.f}, im = re;
         F::template mma<Q>(re, ah, al, rch, rcl);
-        if (!jr) F::template mma<Q>(im, ah, al, rdh, rdl);
+        if constexpr (!jr) F::template mma<Q>(im, ah, al, rdh, rdl);
+        if constexpr (F::drain) f32_mfma_drain(re, im);
         // lane holds J rows 16 b + 4 g + r of column 16 w + o
         const int slot = (16 * b) % RING + 4 * g;
         T* ja = Jst + (16 * w + o) * RP + slot;
@@ -247,8 +285,12 @@ __global__ __launch_bounds__(kThreads) void k_stream(StreamArgs a)
 
     // ---- vertical pass of output rows 16 s .. 16 s + 15, column block w
     const int64_t plane = (int64_t)a.H * a.W;
-    float2* oa = a.out + (int64_t)jb.out_a * plane;
-    float2* ob = jb.out_b >= 0 ? a.out + (int64_t)jb.out_b * plane : nullptr;
+    const uint32_t plane_bytes = (uint32_t)(plane * 8);
+    const __amdgpu_buffer_rsrc_t out_a = make_rsrc(a.out + (int64_t)jb.out_a * plane, plane_bytes);
+    const __amdgpu_buffer_rsrc_t out_b = jb.out_b >= 0
+        ? make_rsrc(a.out + (int64_t)jb.out_b * plane, plane_bytes)
+        : make_rsrc(a.out, 0u);                                 // no partner: every store dropped
+    const int yend = min(a.H, yseg + a.seg_rows);
     auto col_pass = [&](int s) {
         T bah[Q], bal[Q], bbh[Q], bbl[Q];
         const T* base = Jst + (16 * w + o) * RP;
@@ -259,7 +301,7 @@ __global__ __launch_bounds__(kThreads) void k_stream(StreamArgs a)
             const T* src = base + slot;
             *reinterpret_cast<float4*>(bah + p) = *reinterpret_cast<const float4*>(src);
             if (SPLIT) *reinterpret_cast<float4*>(bal + p) = *reinterpret_cast<const float4*>(src + 2 * JPLANE);
-            if (!jr) {
+            if constexpr (!jr) {
                 *reinterpret_cast<float4*>(bbh + p) = *reinterpret_cast<const float4*>(src + JPLANE);
                 if (SPLIT) *reinterpret_cast<float4*>(bbl + p) = *reinterpret_cast<const float4*>(src + 3 * JPLANE);
             }
@@ -268,52 +310,85 @@ __global__ __launch_bounds__(kThreads) void k_stream(StreamArgs a)
         }
         f4_t P1 = {0.f, 0.f, 0.f, 0.f}, P2 = P1, P3 = P1, P4 = P1;
         F::template mma<Q>(P1, cch, ccl, bah, bal);
-        if (!cr) F::template mma<Q>(P3, cdh, cdl, bah, bal);
-        if (!jr) {
+        if constexpr (!cr) F::template mma<Q>(P3, cdh, cdl, bah, bal);
+        if constexpr (!jr) {
             F::template mma<Q>(P4, cch, ccl, bbh, bbl);
-            if (!cr) F::template mma<Q>(P2, cdh, cdl, bbh, bbl);
+            if constexpr (!cr) F::template mma<Q>(P2, cdh, cdl, bbh, bbl);
         }
+        if constexpr (F::drain) f32_mfma_drain(P1, P2, P3, P4);
         const int x = x0 + 16 * w + o;
-        if (x < a.W) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int y = yseg + 16 * s + 4 * g + r;
-                if (y < a.H && 16 * s + 4 * g + r < a.seg_rows) {
-                    const float p1 = P1[r] * a.out_scale, p2 = P2[r] * a.out_scale;
-                    const float p3 = P3[r] * a.out_scale, p4 = P4[r] * a.out_scale;
-                    oa[(int64_t)y * a.W + x] = make_float2(p1 - p2, p3 + p4);
-                    if (ob) ob[(int64_t)y * a.W + x] = make_float2(p1 + p2, p3 - p4);
-                }
-            }
+        for (int r = 0; r < 4; ++r) {
+            const int y = yseg + 16 * s + 4 * g + r;
+            const uint32_t off = (x < a.W && y < yend) ? (uint32_t)(((int64_t)y * a.W + x) * 8) : kOutside;
+            const float p1 = P1[r] * a.out_scale, p2 = P2[r] * a.out_scale;
+            const float p3 = P3[r] * a.out_scale, p4 = P4[r] * a.out_scale;
+            i2_t va, vb;
+            va[0] = __builtin_bit_cast(int, p1 - p2);
+            va[1] = __builtin_bit_cast(int, p3 + p4);
+            vb[0] = __builtin_bit_cast(int, p1 + p2);
+            vb[1] = __builtin_bit_cast(int, p3 - p4);
+            __builtin_amdgcn_raw_buffer_store_b64(va, out_a, (int)off, 0, 0);
+            if constexpr (!JR) __builtin_amdgcn_raw_buffer_store_b64(vb, out_b, (int)off, 0, 0);
         }
     };
 
-    // ---- lead-in: J blocks 0 .. L/16 - 1, then the slab of block L/16
+    // Image slabs travel through two register sets that swap roles every
+    // step (no copies, which would wait for loads still in flight).
     constexpr int LEAD = L / 16;
-    for (int b = 0; b < LEAD; ++b) {
-        slab_load(b);
-        slab_store(b);
-        __syncthreads();
-        row_pass(b);
-    }
-    if (nsteps > 1) {
-        slab_load(LEAD);
-        slab_store(LEAD);
-    }
-    __syncthreads();
+    float pre_a[PER_T], pre_b[PER_T];
 
-    // ---- stream: iteration s computes J block s + LEAD (needed by step
-    // s + 1) and output step s; the slab for the next block is fetched from
-    // memory during the iteration and staged before the barrier.
-    for (int s = 0; s < nsteps; ++s) {
-        const bool more = s + 1 < nsteps;         // block s + LEAD is needed
-        const bool fetch = s + 2 < nsteps;        // block s + LEAD + 1 is needed
-        if (fetch) slab_load(s + LEAD + 1);
-        if (more) row_pass(s + LEAD);
+    // ---- lead-in: J blocks 0 .. LEAD - 1.  Step b stages slab b (loaded
+    // one step earlier), fetches slab b + 1 and computes J block b.
+    auto lead = [&](int b, float (&stg)[PER_T], float (&fet)[PER_T]) {
+        slab_load(b + 1, fet);
+        slab_store(b, stg);
+        lds_barrier();
+        row_pass(b);
+    };
+    // ---- stream: step s computes J block s + LEAD (needed by step s + 1)
+    // and output rows 16 s .. 16 s + 15; it stages the slab of block
+    // s + LEAD + 1 (fetched one step earlier) and fetches the slab of block
+    // s + LEAD + 2, so every load has a whole step to land.  The body has no
+    // branch: work past the segment end reads zeros or folded rows and its
+    // stores fall outside the output resources.
+    auto step = [&](int s, float (&stg)[PER_T], float (&fet)[PER_T]) {
+        slab_load(s + LEAD + 2, fet);
+        row_pass(s + LEAD);
         col_pass(s);
-        if (fetch) slab_store(s + LEAD + 1);
-        __syncthreads();
+        slab_store(s + LEAD + 1, stg);
+        lds_barrier();
+    };
+
+    slab_load(0, pre_a);
+#pragma unroll
+    for (int b = 0; b < LEAD; b += 2) {
+        lead(b, pre_a, pre_b);
+        if (b + 1 < LEAD) lead(b + 1, pre_b, pre_a);
     }
+    // The slab of block LEAD is in pre_a when LEAD is even, else in pre_b.
+    float (&s_lead)[PER_T] = (LEAD % 2 == 0) ? pre_a : pre_b;
+    float (&s_next)[PER_T] = (LEAD % 2 == 0) ? pre_b : pre_a;
+    slab_store(LEAD, s_lead);
+    slab_load(LEAD + 1, s_next);
+    lds_barrier();
+    for (int s = 0; s < nsteps; s += 2) {
+        step(s, s_next, s_lead);
+        step(s + 1, s_lead, s_next);
+    }
+}
+
+template <int OP, int Q>
+__global__ __launch_bounds__(kThreads) void k_stream(StreamArgs a)
+{
+    const int lid = xcd_local_id(blockIdx.x, gridDim.x);
+    const FusedJob jb = a.jobs[lid % a.n_jobs];
+    const int rest = lid / a.n_jobs;
+    // A job whose J and vertical taps are both real (omega = 0) runs the
+    // real-J body with zero sine taps.
+    if (jb.j_real) stream_body<OP, Q, true, false>(a, jb, rest);
+    else if (jb.c_real) stream_body<OP, Q, false, true>(a, jb, rest);
+    else stream_body<OP, Q, false, false>(a, jb, rest);
 }
 
 template <int OP, int Q>

@@ -279,8 +279,10 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
             fws.push_back(ws);
         }
 
+        // The fused kernel addresses the image and each output plane through
+        // 32-bit buffer offsets: planes of at most 2^29 pixels.
         const int q = stream_quarter(p->fused_op, fd.R);
-        const bool fused = q <= kStreamMaxQuarter && algo != ALGO_TWOPASS;
+        const bool fused = q <= kStreamMaxQuarter && algo != ALGO_TWOPASS && npix < (int64_t(1) << 29);
         if (!fused && precision != GABOR_PREC_FP32) {
             release(p);
             return GABOR_ERR_UNSUPPORTED;
@@ -423,6 +425,8 @@ extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int
 {
     if (!p || !d_image || !d_out) return GABOR_ERR_INVALID_ARG;
     if (row_stride_elems < p->W) return GABOR_ERR_INVALID_ARG;
+    if (!p->fjobs.empty() && (int64_t)(p->H - 1) * row_stride_elems + p->W >= (int64_t(1) << 30))
+        return GABOR_ERR_UNSUPPORTED;   // image span past the 32-bit buffer offsets of the fused kernel
     hipStream_t stream = (hipStream_t)hip_stream;
     for (const RowGroup& g : p->row_groups) {
         LaunchTimer tm(p, stream, "row_fp32");
