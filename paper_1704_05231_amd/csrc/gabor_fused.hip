@@ -44,16 +44,18 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 constexpr int kSX = 64;           // strip width: four 16-column blocks, one per wave
 constexpr int kThreads = 256;
 
-// Operand storage and matrix-core step for each arithmetic form.
+// Operand storage and matrix-core step for each arithmetic form.  A pack
+// is what one lane feeds one instruction: a float (FP32) or eight 16-bit
+// values in 16 bytes.  A fragment of Q consecutive values is Q / PER packs;
+// split forms hold a hi and a lo fragment.
 template <int OP> struct Form;
 
 // Wait until the last FP32 matrix-core result is written before any vector
 // instruction reads it.  The compiler schedules reads of a
 // v_mfma_f32_16x16x4_f32 result 10 wait states after the instruction, and on
 // gfx950 such reads of the last accumulator register returned stale values;
-// 16 wait states behind scheduling barriers remove the race.
-// The accumulators are asm operands kept in AGPRs, so no copy of them can
-// be placed before the wait.
+// 16 wait states remove the race.  The accumulators are asm operands kept in
+// AGPRs, so no copy of them can be placed before the wait.
 __device__ __forceinline__ void f32_mfma_drain(f4_t& x, f4_t& y)
 {
     asm volatile("s_nop 7\n\ts_nop 7" : "+a"(x), "+a"(y));
@@ -64,61 +66,90 @@ __device__ __forceinline__ void f32_mfma_drain(f4_t& x, f4_t& y, f4_t& z, f4_t& 
 }
 
 template <> struct Form<FUSED_F32> {
-    using T = float;
+    using T = float;                      // LDS element
+    using Pack = float;
+    static constexpr int PER = 1;         // values per pack
     static constexpr bool split = false;
     static constexpr bool drain = true;
-    static constexpr int per_mma = 1;     // k values per lane per instruction
-    static __device__ __forceinline__ void cvt(float x, T& hi, T& lo) { hi = x; lo = 0.0f; }
-    template <int Q>
-    static __device__ __forceinline__ void mma(f4_t& acc, const T* ah, const T* al, const T* bh, const T* bl)
+    static constexpr bool scaled = false; // range scaling (float16 only)
+    // n consecutive floats -> packs (hi only)
+    template <int N>
+    static __device__ __forceinline__ void pack(const float (&x)[N], Pack* hi, Pack* lo)
+    {
+        (void)lo;
+#pragma unroll
+        for (int e = 0; e < N; ++e) hi[e] = x[e];
+    }
+    static __device__ __forceinline__ void mma1(f4_t& acc, Pack ah, Pack al, Pack bh, Pack bl)
     {
         (void)al; (void)bl;
-#pragma unroll
-        for (int m = 0; m < Q; ++m) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[m], bh[m], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ah, bh, acc, 0, 0, 0);
+    }
+    // two floats -> LDS words (used for image slabs and J rows)
+    typedef float W2 __attribute__((ext_vector_type(2)));
+    static __device__ __forceinline__ void cvt2(float x0, float x1, W2& hi, W2& lo)
+    {
+        hi[0] = x0; hi[1] = x1; lo = hi;
     }
 };
 
-template <typename E> struct Vec8;
-template <> struct Vec8<__bf16> { typedef __bf16 type __attribute__((ext_vector_type(8))); };
-template <> struct Vec8<_Float16> { typedef _Float16 type __attribute__((ext_vector_type(8))); };
+template <typename E> struct Vec;
+template <> struct Vec<__bf16> {
+    typedef __bf16 v8 __attribute__((ext_vector_type(8)));
+    typedef __bf16 v2 __attribute__((ext_vector_type(2)));
+};
+template <> struct Vec<_Float16> {
+    typedef _Float16 v8 __attribute__((ext_vector_type(8)));
+    typedef _Float16 v2 __attribute__((ext_vector_type(2)));
+};
 
-__device__ __forceinline__ f4_t mfma16(f4_t acc, Vec8<__bf16>::type a, Vec8<__bf16>::type b)
+__device__ __forceinline__ f4_t mfma16(f4_t acc, Vec<__bf16>::v8 a, Vec<__bf16>::v8 b)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
 }
-__device__ __forceinline__ f4_t mfma16(f4_t acc, Vec8<_Float16>::type a, Vec8<_Float16>::type b)
+__device__ __forceinline__ f4_t mfma16(f4_t acc, Vec<_Float16>::v8 a, Vec<_Float16>::v8 b)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc, 0, 0, 0);
 }
 
 template <typename E, bool SPLIT> struct Form16 {
     using T = E;
+    using Pack = typename Vec<E>::v8;
+    static constexpr int PER = 8;
     static constexpr bool split = SPLIT;
     static constexpr bool drain = false;
-    static constexpr int per_mma = 8;
-    static __device__ __forceinline__ void cvt(float x, T& hi, T& lo)
-    {
-        hi = (T)x;
-        lo = SPLIT ? (T)(x - (float)hi) : (T)0.0f;
-    }
-    using V = typename Vec8<E>::type;
-    static __device__ __forceinline__ f4_t one(f4_t acc, const T* a, const T* b)
-    {
-        V va, vb;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) { va[e] = a[e]; vb[e] = b[e]; }
-        return mfma16(acc, va, vb);
-    }
-    template <int Q>
-    static __device__ __forceinline__ void mma(f4_t& acc, const T* ah, const T* al, const T* bh, const T* bl)
+    static constexpr bool scaled = __is_same(E, _Float16);
+    template <int N>
+    static __device__ __forceinline__ void pack(const float (&x)[N], Pack* hi, Pack* lo)
     {
 #pragma unroll
-        for (int m = 0; m < Q; m += 8) {
-            if (SPLIT) {
-                acc = one(acc, al + m, bh + m);
-                acc = one(acc, ah + m, bl + m);
+        for (int p = 0; p < N / 8; ++p)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const E h = (E)x[8 * p + e];
+                hi[p][e] = h;
+                if (SPLIT) lo[p][e] = (E)(x[8 * p + e] - (float)h);
             }
-            acc = one(acc, ah + m, bh + m);
+    }
+    static __device__ __forceinline__ void mma1(f4_t& acc, const Pack& ah, const Pack& al,
+                                                const Pack& bh, const Pack& bl)
+    {
+        if (SPLIT) {
+            acc = mfma16(acc, al, bh);
+            acc = mfma16(acc, ah, bl);
+        }
+        acc = mfma16(acc, ah, bh);
+    }
+    typedef typename Vec<E>::v2 W2;
+    static __device__ __forceinline__ void cvt2(float x0, float x1, W2& hi, W2& lo)
+    {
+        hi[0] = (E)x0;
+        hi[1] = (E)x1;
+        if (SPLIT) {
+            lo[0] = (E)(x0 - (float)hi[0]);
+            lo[1] = (E)(x1 - (float)hi[1]);
+        } else {
+            lo = hi;
         }
     }
 };
@@ -137,6 +168,19 @@ __device__ __forceinline__ int fold_index(int i, int n, int boundary)
     int r = i % p;
     if (r < 0) r += p;
     return r < n ? r : p - r;
+}
+
+// Same mapping as fold_index without division: one reflection covers every
+// index within one image length of the edge, and the rare further
+// reflections (R larger than the image side) run in a loop, which keeps the
+// compiler from turning the uncommon path into straight-line code.
+__device__ __forceinline__ int fold_cheap(int i, int n, int boundary)
+{
+    if ((unsigned)i < (unsigned)n) return i;
+    if (boundary == 0) return -1;
+    if (n == 1) return 0;
+    while ((unsigned)i >= (unsigned)n) i = i < 0 ? -i : 2 * (n - 1) - i;
+    return i;
 }
 
 // Workgroup id remap: the hardware deals consecutive ids round-robin to the
@@ -168,16 +212,6 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint3
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
 
-// 16-byte LDS copies of Q consecutive operand values.
-template <typename T, int Q>
-__device__ __forceinline__ void lds_get(T* dst, const T* src)
-{
-    constexpr int per = 16 / sizeof(T);
-    static_assert(Q % per == 0, "quarter must be whole 16-byte pieces");
-#pragma unroll
-    for (int p = 0; p < Q; p += per) *reinterpret_cast<float4*>(dst + p) = *reinterpret_cast<const float4*>(src + p);
-}
-
 // JR: J is real (horizontal taps have no sine part); CR: vertical taps have
 // no sine part.  Both are compile-time so that no branch separates a
 // matrix-core chain from the reads of its result.
@@ -186,7 +220,10 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
 {
     using F = Form<OP>;
     using T = typename F::T;
+    using Pack = typename F::Pack;
+    using W2 = typename F::W2;
     constexpr bool SPLIT = F::split;
+    constexpr int NP = Q / F::PER;           // packs per fragment
     constexpr int L = 4 * Q;                 // contracted length per 16-block
     constexpr int RING = L + 16;             // J rows held
     constexpr int PAD = 16 / sizeof(T);
@@ -195,91 +232,151 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
     constexpr int WP = WF + PAD;
     constexpr int NPL = SPLIT ? 2 : 1;       // hi (+ lo) copies
     constexpr int JPLANE = kSX * RP;         // one J component of one copy
-    constexpr int FROWS = ((16 * WF + kThreads - 1) / kThreads * kThreads + WF - 1) / WF;
+    constexpr int SLAB2 = 16 * WF / 2;       // column pairs per slab
+    constexpr int PER_T = (SLAB2 + kThreads - 1) / kThreads;
+    constexpr int FROWS = (2 * PER_T * kThreads + WF - 1) / WF;
     constexpr int FBUF = FROWS * WP;         // one slab of one copy (+ padding rows)
+    static_assert(16 % sizeof(T) == 0 && Q % (16 / sizeof(T)) == 0, "16-byte pieces");
 
     extern __shared__ float4 stream_lds4[];
     T* Jst = reinterpret_cast<T*>(stream_lds4);             // [NPL][2 comps][kSX][RP]
-    T* Fst = Jst + NPL * 2 * JPLANE;                         // [NPL][2 bufs][16][WP]
+    T* Fst = Jst + NPL * 2 * JPLANE;                         // [NPL][2 bufs][FROWS][WP]
 
-    const int rest = job_rest;
-    const int xs = rest % a.n_xs, ys = rest / a.n_xs;
+    const int xs = job_rest % a.n_xs, ys = job_rest / a.n_xs;
     const int x0 = xs * kSX, yseg = ys * a.seg_rows;
     const int nsteps = (min(a.seg_rows, a.H - yseg) + 15) / 16;
     const int R = a.R;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int o = lane & 15, g = lane >> 4;
-    constexpr bool jr = JR, cr = CR;
     const float* tab = a.taps + jb.tap_off;                  // [4][L + 16]: row c, row d, col c, col d
     constexpr int KT = L + 16;
+    // float16 range scales (all exactly 1 for the other forms)
+    const float in_s = F::scaled ? a.in_scale : 1.0f, mid_s = F::scaled ? a.mid_scale : 1.0f;
+    const float out_s = F::scaled ? a.out_scale : 1.0f;
+    const float rt_s = F::scaled ? a.tap_scale[0] : 1.0f, ct_s = F::scaled ? a.tap_scale[1] : 1.0f;
+    auto sc = [](float x, float k) { return F::scaled ? x * k : x; };
 
     // Band fragments: lane (o, g) holds krev[Q g + e - o], e = 0..Q-1
     // (entry m of a table holds krev[m - 16]).
-    T rch[Q], rcl[Q], rdh[Q], rdl[Q], cch[Q], ccl[Q], cdh[Q], cdl[Q];
+    Pack rch[NP], rcl[NP], rdh[NP], rdl[NP], cch[NP], ccl[NP], cdh[NP], cdl[NP];
+    {
+        float x0v[Q], x1v[Q], x2v[Q], x3v[Q];
 #pragma unroll
-    for (int e = 0; e < Q; ++e) {
-        const int m = 16 + Q * g + e - o;
-        F::cvt(tab[m] * a.tap_scale[0], rch[e], rcl[e]);
-        F::cvt(tab[KT + m] * a.tap_scale[0], rdh[e], rdl[e]);
-        F::cvt(tab[2 * KT + m] * a.tap_scale[1], cch[e], ccl[e]);
-        F::cvt(tab[3 * KT + m] * a.tap_scale[1], cdh[e], cdl[e]);
+        for (int e = 0; e < Q; ++e) {
+            const int m = 16 + Q * g + e - o;
+            x0v[e] = sc(tab[m], rt_s);
+            x1v[e] = sc(tab[KT + m], rt_s);
+            x2v[e] = sc(tab[2 * KT + m], ct_s);
+            x3v[e] = sc(tab[3 * KT + m], ct_s);
+        }
+        F::template pack<Q>(x0v, rch, rcl);
+        F::template pack<Q>(x1v, rdh, rdl);
+        F::template pack<Q>(x2v, cch, ccl);
+        F::template pack<Q>(x3v, cdh, cdl);
     }
 
-    // ---- image slab staging: rows yseg - R + 16 b + i, columns x0 - R + c
-    // (lanes past the slab read nothing and write the padding rows).
-    constexpr int SLAB = 16 * WF;
-    constexpr int PER_T = (SLAB + kThreads - 1) / kThreads;
+    // ---- image slab staging, by column pairs: rows yseg - R + 16 b + i,
+    // columns x0 - R + c (lanes past the slab read nothing and write the
+    // padding rows).
     const __amdgpu_buffer_rsrc_t img_rsrc =
         make_rsrc(a.img, (uint32_t)(((int64_t)(a.H - 1) * a.stride + a.W) * 4));
-    auto slab_load = [&](int b, float (&pre)[PER_T]) {
+    // Per thread and pair k: the folded columns (fixed for the strip), the
+    // offset relative to the slab's first row when no row or column folds
+    // (rel), and the LDS position.
+    int col_of[2 * PER_T], rel[2 * PER_T], lds_at[PER_T], row_of[PER_T];
+    const bool cols_inside = x0 - R >= 0 && x0 - R + WF <= a.W;
 #pragma unroll
-        for (int k = 0; k < PER_T; ++k) {
-            const int idx = tid + k * kThreads;
-            const int r = idx / WF, c = idx - r * WF;
-            const int yy = fold_index(yseg - R + 16 * b + r, a.H, a.boundary);
-            const int xx = fold_index(x0 - R + c, a.W, a.boundary);
-            const uint32_t off = (idx < SLAB && yy >= 0 && xx >= 0)
-                                     ? (uint32_t)(((int64_t)yy * a.stride + xx) * 4) : kOutside;
-            pre[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(img_rsrc, (int)off, 0, 0));
+    for (int k = 0; k < PER_T; ++k) {
+        const int idx = tid + k * kThreads;
+        const int e = 2 * idx;
+        const int r = e / WF, c = e - r * WF;
+        const bool live = idx < SLAB2;
+        row_of[k] = r;
+        lds_at[k] = r * WP + c;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            col_of[2 * k + h] = live ? fold_index(x0 - R + c + h, a.W, a.boundary) : -1;
+            rel[2 * k + h] = live ? r * a.stride + (x0 - R + c + h) : -1;
+        }
+    }
+    auto slab_load = [&](int b, float (&pre)[2 * PER_T]) {
+        const int row0 = yseg - R + 16 * b;
+        if (cols_inside && row0 >= 0 && row0 + 16 <= a.H) {
+            // interior: no folding, one add per element
+            const uint32_t base = (uint32_t)row0 * (uint32_t)a.stride;
+#pragma unroll
+            for (int k = 0; k < 2 * PER_T; ++k) {
+                const uint32_t off = rel[k] >= 0 ? (base + (uint32_t)rel[k]) * 4u : kOutside;
+                pre[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(img_rsrc, (int)off, 0, 0));
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < PER_T; ++k) {
+                const int yy = fold_cheap(row0 + row_of[k], a.H, a.boundary);
+                const uint32_t rowoff = (uint32_t)yy * (uint32_t)a.stride;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int cx = col_of[2 * k + h];
+                    const uint32_t off = (yy >= 0 && cx >= 0) ? (rowoff + (uint32_t)cx) * 4u : kOutside;
+                    pre[2 * k + h] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(img_rsrc, (int)off, 0, 0));
+                }
+            }
         }
     };
-    auto slab_store = [&](int b, const float (&pre)[PER_T]) {
+    auto slab_store = [&](int b, const float (&pre)[2 * PER_T]) {
         T* hi = Fst + (b & 1) * FBUF;
         T* lo = hi + 2 * FBUF;
 #pragma unroll
         for (int k = 0; k < PER_T; ++k) {
-            const int idx = tid + k * kThreads;
-            const int r = idx / WF, c = idx - r * WF;
-            T h, l;
-            F::cvt(pre[k] * a.in_scale, h, l);
-            hi[r * WP + c] = h;
-            if (SPLIT) lo[r * WP + c] = l;
+            W2 h, l;
+            F::cvt2(sc(pre[2 * k], in_s), sc(pre[2 * k + 1], in_s), h, l);
+            *reinterpret_cast<W2*>(hi + lds_at[k]) = h;
+            if (SPLIT) *reinterpret_cast<W2*>(lo + lds_at[k]) = l;
         }
+    };
+
+    // 16-byte LDS reads straight into operand packs.
+    auto frag_get = [&](Pack* dst, const T* src) {
+#pragma unroll
+        for (int p = 0; p < Q; p += PAD)
+            *reinterpret_cast<float4*>(reinterpret_cast<T*>(dst) + p) = *reinterpret_cast<const float4*>(src + p);
     };
 
     // ---- horizontal pass of J block b (16 rows) for column block w
     auto row_pass = [&](int b) {
         const T* fh = Fst + (b & 1) * FBUF + o * WP + 16 * w + Q * g;
-        const T* fl = fh + 2 * FBUF;
-        T ah[Q], al[Q];
-        lds_get<T, Q>(ah, fh);
-        if (SPLIT) lds_get<T, Q>(al, fl);
+        Pack ah[NP], al[NP];
+        frag_get(ah, fh);
+        if (SPLIT) frag_get(al, fh + 2 * FBUF);
         f4_t re = {0.f, 0.f, 0.f, 0.f}, im = re;
-        F::template mma<Q>(re, ah, al, rch, rcl);
-        if constexpr (!jr) F::template mma<Q>(im, ah, al, rdh, rdl);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            F::mma1(re, ah[p], al[p], rch[p], rcl[p]);
+            if constexpr (!JR) F::mma1(im, ah[p], al[p], rdh[p], rdl[p]);
+        }
         if constexpr (F::drain) f32_mfma_drain(re, im);
-        // lane holds J rows 16 b + 4 g + r of column 16 w + o
+        // lane holds J rows 16 b + 4 g + r of column 16 w + o: four
+        // consecutive ring entries per component and copy
         const int slot = (16 * b) % RING + 4 * g;
         T* ja = Jst + (16 * w + o) * RP + slot;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            T h, l;
-            F::cvt(re[r] * a.mid_scale, h, l);
-            ja[r] = h;                                  // hi, real part
-            if (SPLIT) ja[2 * JPLANE + r] = l;          // lo, real part
-            F::cvt(im[r] * a.mid_scale, h, l);
-            ja[JPLANE + r] = h;                         // hi, imaginary part
-            if (SPLIT) ja[3 * JPLANE + r] = l;          // lo, imaginary part
+        W2 h0, l0, h1, l1;
+        F::cvt2(sc(re[0], mid_s), sc(re[1], mid_s), h0, l0);
+        F::cvt2(sc(re[2], mid_s), sc(re[3], mid_s), h1, l1);
+        reinterpret_cast<W2*>(ja)[0] = h0;
+        reinterpret_cast<W2*>(ja)[1] = h1;
+        if (SPLIT) {
+            reinterpret_cast<W2*>(ja + 2 * JPLANE)[0] = l0;
+            reinterpret_cast<W2*>(ja + 2 * JPLANE)[1] = l1;
+        }
+        if constexpr (!JR) {
+            F::cvt2(sc(im[0], mid_s), sc(im[1], mid_s), h0, l0);
+            F::cvt2(sc(im[2], mid_s), sc(im[3], mid_s), h1, l1);
+            reinterpret_cast<W2*>(ja + JPLANE)[0] = h0;
+            reinterpret_cast<W2*>(ja + JPLANE)[1] = h1;
+            if (SPLIT) {
+                reinterpret_cast<W2*>(ja + 3 * JPLANE)[0] = l0;
+                reinterpret_cast<W2*>(ja + 3 * JPLANE)[1] = l1;
+            }
         }
     };
 
@@ -292,28 +389,30 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
         : make_rsrc(a.out, 0u);                                 // no partner: every store dropped
     const int yend = min(a.H, yseg + a.seg_rows);
     auto col_pass = [&](int s) {
-        T bah[Q], bal[Q], bbh[Q], bbl[Q];
+        Pack bah[NP], bal[NP], bbh[NP], bbl[NP];
         const T* base = Jst + (16 * w + o) * RP;
-        constexpr int per = 16 / sizeof(T);
         int slot = (16 * s + Q * g) % RING;
 #pragma unroll
-        for (int p = 0; p < Q; p += per) {
+        for (int p = 0; p < Q; p += PAD) {
             const T* src = base + slot;
-            *reinterpret_cast<float4*>(bah + p) = *reinterpret_cast<const float4*>(src);
-            if (SPLIT) *reinterpret_cast<float4*>(bal + p) = *reinterpret_cast<const float4*>(src + 2 * JPLANE);
-            if constexpr (!jr) {
-                *reinterpret_cast<float4*>(bbh + p) = *reinterpret_cast<const float4*>(src + JPLANE);
-                if (SPLIT) *reinterpret_cast<float4*>(bbl + p) = *reinterpret_cast<const float4*>(src + 3 * JPLANE);
+            *reinterpret_cast<float4*>(reinterpret_cast<T*>(bah) + p) = *reinterpret_cast<const float4*>(src);
+            if (SPLIT) *reinterpret_cast<float4*>(reinterpret_cast<T*>(bal) + p) = *reinterpret_cast<const float4*>(src + 2 * JPLANE);
+            if constexpr (!JR) {
+                *reinterpret_cast<float4*>(reinterpret_cast<T*>(bbh) + p) = *reinterpret_cast<const float4*>(src + JPLANE);
+                if (SPLIT) *reinterpret_cast<float4*>(reinterpret_cast<T*>(bbl) + p) = *reinterpret_cast<const float4*>(src + 3 * JPLANE);
             }
-            slot += per;
+            slot += PAD;
             if (slot >= RING) slot -= RING;
         }
         f4_t P1 = {0.f, 0.f, 0.f, 0.f}, P2 = P1, P3 = P1, P4 = P1;
-        F::template mma<Q>(P1, cch, ccl, bah, bal);
-        if constexpr (!cr) F::template mma<Q>(P3, cdh, cdl, bah, bal);
-        if constexpr (!jr) {
-            F::template mma<Q>(P4, cch, ccl, bbh, bbl);
-            if constexpr (!cr) F::template mma<Q>(P2, cdh, cdl, bbh, bbl);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            F::mma1(P1, cch[p], ccl[p], bah[p], bal[p]);
+            if constexpr (!CR) F::mma1(P3, cdh[p], cdl[p], bah[p], bal[p]);
+            if constexpr (!JR) {
+                F::mma1(P4, cch[p], ccl[p], bbh[p], bbl[p]);
+                if constexpr (!CR) F::mma1(P2, cdh[p], cdl[p], bbh[p], bbl[p]);
+            }
         }
         if constexpr (F::drain) f32_mfma_drain(P1, P2, P3, P4);
         const int x = x0 + 16 * w + o;
@@ -321,8 +420,8 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
         for (int r = 0; r < 4; ++r) {
             const int y = yseg + 16 * s + 4 * g + r;
             const uint32_t off = (x < a.W && y < yend) ? (uint32_t)(((int64_t)y * a.W + x) * 8) : kOutside;
-            const float p1 = P1[r] * a.out_scale, p2 = P2[r] * a.out_scale;
-            const float p3 = P3[r] * a.out_scale, p4 = P4[r] * a.out_scale;
+            const float p1 = sc(P1[r], out_s), p2 = sc(P2[r], out_s);
+            const float p3 = sc(P3[r], out_s), p4 = sc(P4[r], out_s);
             i2_t va, vb;
             va[0] = __builtin_bit_cast(int, p1 - p2);
             va[1] = __builtin_bit_cast(int, p3 + p4);
@@ -336,11 +435,11 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
     // Image slabs travel through two register sets that swap roles every
     // step (no copies, which would wait for loads still in flight).
     constexpr int LEAD = L / 16;
-    float pre_a[PER_T], pre_b[PER_T];
+    float pre_a[2 * PER_T], pre_b[2 * PER_T];
 
     // ---- lead-in: J blocks 0 .. LEAD - 1.  Step b stages slab b (loaded
     // one step earlier), fetches slab b + 1 and computes J block b.
-    auto lead = [&](int b, float (&stg)[PER_T], float (&fet)[PER_T]) {
+    auto lead = [&](int b, float (&stg)[2 * PER_T], float (&fet)[2 * PER_T]) {
         slab_load(b + 1, fet);
         slab_store(b, stg);
         lds_barrier();
@@ -352,7 +451,7 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
     // s + LEAD + 2, so every load has a whole step to land.  The body has no
     // branch: work past the segment end reads zeros or folded rows and its
     // stores fall outside the output resources.
-    auto step = [&](int s, float (&stg)[PER_T], float (&fet)[PER_T]) {
+    auto step = [&](int s, float (&stg)[2 * PER_T], float (&fet)[2 * PER_T]) {
         slab_load(s + LEAD + 2, fet);
         row_pass(s + LEAD);
         col_pass(s);
@@ -367,8 +466,8 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
         if (b + 1 < LEAD) lead(b + 1, pre_b, pre_a);
     }
     // The slab of block LEAD is in pre_a when LEAD is even, else in pre_b.
-    float (&s_lead)[PER_T] = (LEAD % 2 == 0) ? pre_a : pre_b;
-    float (&s_next)[PER_T] = (LEAD % 2 == 0) ? pre_b : pre_a;
+    float (&s_lead)[2 * PER_T] = (LEAD % 2 == 0) ? pre_a : pre_b;
+    float (&s_next)[2 * PER_T] = (LEAD % 2 == 0) ? pre_b : pre_a;
     slab_store(LEAD, s_lead);
     slab_load(LEAD + 1, s_next);
     lds_barrier();
@@ -446,7 +545,9 @@ size_t stream_lds_bytes(int op, int Q)
     const size_t es = op == FUSED_F32 ? 4 : 2;
     const int pad = (int)(16 / es);
     const size_t npl = (op == FUSED_BF16X3 || op == FUSED_F16X3) ? 2 : 1;
-    return npl * es * (2 * (size_t)kSX * (RING + pad) + 2 * 16 * (size_t)(WF + pad));
+    const int per_t = (16 * WF / 2 + kThreads - 1) / kThreads;
+    const int frows = (2 * per_t * kThreads + WF - 1) / WF;
+    return npl * es * (2 * (size_t)kSX * (RING + pad) + 2 * (size_t)frows * (WF + pad));
 }
 
 int stream_strip_width() { return kSX; }

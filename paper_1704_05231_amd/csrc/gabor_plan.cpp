@@ -56,6 +56,10 @@ struct gabor_plan_s {
     ColJob* d_jobs = nullptr;
     FusedJob* d_fjobs = nullptr;
     float2* d_J = nullptr;
+    // Fork/join of the per-frequency launches: auxiliary streams (default
+    // priority) joined back to the caller's stream with events.
+    std::vector<hipStream_t> aux;
+    std::vector<hipEvent_t> fork_ev, join_ev;
     // per-kernel timing
     bool prof = false;
     struct Pending { int kind; hipEvent_t a, b; };
@@ -104,6 +108,9 @@ void release(gabor_plan p)
     if (p->d_jobs) (void)hipFree(p->d_jobs);
     if (p->d_fjobs) (void)hipFree(p->d_fjobs);
     if (p->d_J) (void)hipFree(p->d_J);
+    for (hipStream_t st : p->aux) (void)hipStreamDestroy(st);
+    for (hipEvent_t e : p->fork_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : p->join_ev) (void)hipEventDestroy(e);
     delete p;
 }
 
@@ -416,6 +423,19 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
         release(p);
         return GABOR_ERR_DEVICE;
     }
+    // Independent frequencies run concurrently: up to three auxiliary
+    // streams beside the caller's (four hardware queues).
+    const int n_conc = std::min<int>(3, (int)p->order.size() - 1);
+    for (int k = 0; k < n_conc; ++k) {
+        hipStream_t st = nullptr;
+        hipEvent_t e1 = nullptr, e2 = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) { release(p); return GABOR_ERR_DEVICE; }
+        p->aux.push_back(st);
+        if (hipEventCreateWithFlags(&e1, hipEventDisableTiming) != hipSuccess) { release(p); return GABOR_ERR_DEVICE; }
+        p->fork_ev.push_back(e1);
+        if (hipEventCreateWithFlags(&e2, hipEventDisableTiming) != hipSuccess) { release(p); return GABOR_ERR_DEVICE; }
+        p->join_ev.push_back(e2);
+    }
     *out = p;
     return GABOR_OK;
 }
@@ -434,11 +454,19 @@ extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int
                             p->d_taps, p->d_J, stream) != hipSuccess)
             return GABOR_ERR_DEVICE;
     }
-    // Heaviest frequencies (largest R) first.
-    for (int i : p->order) {
+    // Heaviest frequencies (largest R) first; launch j > 0 goes to
+    // auxiliary stream (j - 1) mod n, which first waits for the work already
+    // queued on the caller's stream (the image may have just been written).
+    const int n_aux = (int)p->aux.size();
+    if (n_aux > 0 && hipEventRecord(p->fork_ev[0], stream) != hipSuccess) return GABOR_ERR_DEVICE;
+    for (int k = 0; k < n_aux; ++k)
+        if (hipStreamWaitEvent(p->aux[k], p->fork_ev[0], 0) != hipSuccess) return GABOR_ERR_DEVICE;
+    for (size_t j = 0; j < p->order.size(); ++j) {
+        const int i = p->order[j];
         const FreqLaunch& fl = p->launches[i];
+        hipStream_t ls = (j == 0 || n_aux == 0) ? stream : p->aux[(j - 1) % n_aux];
         if (fl.fused) {
-            LaunchTimer tm(p, stream, kFusedNames[p->fused_op]);
+            LaunchTimer tm(p, ls, kFusedNames[p->fused_op]);
             StreamArgs sa{};
             sa.img = d_image;
             sa.stride = row_stride_elems;
@@ -458,13 +486,18 @@ extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int
             sa.out_scale = fl.out_scale;
             sa.tap_scale[0] = fl.tap_scale[0];
             sa.tap_scale[1] = fl.tap_scale[1];
-            if (launch_stream(p->fused_op, sa, fl.q, stream) != hipSuccess) return GABOR_ERR_DEVICE;
+            if (launch_stream(p->fused_op, sa, fl.q, ls) != hipSuccess) return GABOR_ERR_DEVICE;
         } else {
-            LaunchTimer tm(p, stream, "col_fp32");
+            LaunchTimer tm(p, ls, "col_fp32");
             if (launch_col_fp32(p->d_J, p->H, p->W, p->boundary, p->freqs[i], p->d_jobs + fl.first,
-                                fl.count, p->d_taps, (float2*)d_out, stream) != hipSuccess)
+                                fl.count, p->d_taps, (float2*)d_out, ls) != hipSuccess)
                 return GABOR_ERR_DEVICE;
         }
+    }
+    for (int k = 0; k < n_aux; ++k) {
+        if (hipEventRecord(p->join_ev[k], p->aux[k]) != hipSuccess ||
+            hipStreamWaitEvent(stream, p->join_ev[k], 0) != hipSuccess)
+            return GABOR_ERR_DEVICE;
     }
     return GABOR_OK;
 }
