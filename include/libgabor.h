@@ -141,9 +141,13 @@ gabor_status gabor_bank_plan_info(gabor_plan plan, gabor_plan_info* info);
  * (n_stats receives the number of kernels seen).  Host pointers.
  */
 typedef struct gabor_kernel_stat {
-    char name[32];       /* kernel name, e.g. "row_fp32" */
+    char name[32];       /* kernel and radius, e.g. "stream_bf16x3_r48" */
     int64_t launches;    /* launches timed */
     double total_ms;     /* sum of event-measured launch durations */
+    int64_t real_macs;   /* algorithmic real multiply-adds of one launch
+                            (K taps per real 1-D pass per pixel) */
+    int64_t bytes;       /* algorithmic memory bytes of one launch: what its
+                            inputs and outputs must move at least once */
 } gabor_kernel_stat;
 
 gabor_status gabor_profile_enable(gabor_plan plan, int32_t enable);

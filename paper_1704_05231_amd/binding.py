@@ -48,20 +48,23 @@ class PlanInfo(ctypes.Structure):
 
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
-                ("total_ms", ctypes.c_double)]
+                ("total_ms", ctypes.c_double), ("real_macs", ctypes.c_int64),
+                ("bytes", ctypes.c_int64)]
 
 
 _lib = None
 
 
 def load():
-    """Load libgabor.so (built in-tree by paper_1704_05231_amd.build)."""
+    """Load libgabor.so (built in-tree by paper_1704_05231_amd.build;
+    LIBGABOR_LIBRARY may name another build of the same ABI)."""
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_1704_05231_amd.build")
-    lib = ctypes.CDLL(LIB_PATH)
+    path = os.environ.get("LIBGABOR_LIBRARY", LIB_PATH)
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run python -m paper_1704_05231_amd.build")
+    lib = ctypes.CDLL(path)
     P, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     lib.gabor_status_string.argtypes = [ctypes.c_int]
     lib.gabor_status_string.restype = ctypes.c_char_p
@@ -146,12 +149,14 @@ def gabor_profile_enable(plan, enable: bool):
 
 
 def gabor_profile_read(plan) -> dict:
-    """{kernel name: (launches, total_ms)} of the launches timed so far."""
-    cap = 16
+    """{kernel name: {launches, total_ms, real_macs, bytes}} of the launches
+    timed so far (real_macs and bytes are algorithmic, per launch)."""
+    cap = 64
     arr = (KernelStat * cap)()
     n = ctypes.c_int32()
     _check(load().gabor_profile_read(plan, arr, cap, ctypes.byref(n)), "gabor_profile_read")
-    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms))
+    return {arr[i].name.decode(): {"launches": int(arr[i].launches), "total_ms": float(arr[i].total_ms),
+                                   "real_macs": int(arr[i].real_macs), "bytes": int(arr[i].bytes)}
             for i in range(min(n.value, cap))}
 
 

@@ -32,6 +32,8 @@ struct FreqLaunch {
     float in_scale, mid_scale, out_scale, tap_scale[2];
     int first;        // first job
     int count;        // jobs
+    int64_t macs;     // algorithmic real MACs of the launch (vertical, plus horizontal when fused)
+    int64_t bytes;    // algorithmic bytes of the launch
 };
 const char* const kFusedNames[5] = {"stream_f32", "stream_bf16", "stream_bf16x3", "stream_f16", "stream_f16x3"};
 enum { ALGO_AUTO = 0, ALGO_TWOPASS = 1 };
@@ -43,6 +45,7 @@ struct gabor_plan_s {
     int32_t precision = 0;
     std::vector<FreqDesc> freqs;
     std::vector<RowGroup> row_groups;
+    std::vector<int64_t> row_group_macs;       // per row group
     std::vector<ColJob> jobs;              // two-pass vertical jobs
     std::vector<FusedJob> fjobs;           // fused jobs
     std::vector<FreqLaunch> launches;      // per frequency
@@ -126,13 +129,15 @@ hipEvent_t take_event(gabor_plan p)
     return e;
 }
 
-int kind_index(gabor_plan p, const char* name)
+int kind_index(gabor_plan p, const std::string& name, int64_t macs, int64_t bytes)
 {
     for (size_t i = 0; i < p->kind_names.size(); ++i)
         if (p->kind_names[i] == name) return (int)i;
     p->kind_names.push_back(name);
     gabor_kernel_stat st{};
-    std::strncpy(st.name, name, sizeof(st.name) - 1);
+    std::strncpy(st.name, name.c_str(), sizeof(st.name) - 1);
+    st.real_macs = macs;
+    st.bytes = bytes;
     p->stats.push_back(st);
     return (int)p->kind_names.size() - 1;
 }
@@ -143,10 +148,11 @@ struct LaunchTimer {
     hipStream_t s;
     int kind = -1;
     hipEvent_t a = nullptr, b = nullptr;
-    LaunchTimer(gabor_plan plan, hipStream_t stream, const char* name) : p(plan), s(stream)
+    LaunchTimer(gabor_plan plan, hipStream_t stream, const std::string& name, int64_t macs, int64_t bytes)
+        : p(plan), s(stream)
     {
         if (!p->prof) return;
-        kind = kind_index(p, name);
+        kind = kind_index(p, name, macs, bytes);
         a = take_event(p);
         b = take_event(p);
         if (a && b && hipEventRecord(a, s) == hipSuccess) return;
@@ -288,6 +294,12 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
 
         // The fused kernel addresses the image and each output plane through
         // 32-bit buffer offsets: planes of at most 2^29 pixels.
+        int64_t f_row_macs = 0, f_col_macs = 0, f_outs = 0;
+        for (const ColJob& jb : fjobs) {
+            f_row_macs += (int64_t)(jb.j_real ? 1 : 2) * fd.K * npix;
+            f_col_macs += (int64_t)((jb.c_real ? 1 : 2) * (jb.j_real ? 1 : 2)) * fd.K * npix;
+            f_outs += (jb.out_b >= 0 ? 2 : 1) * npix;
+        }
         const int q = stream_quarter(p->fused_op, fd.R);
         const bool fused = q <= kStreamMaxQuarter && algo != ALGO_TWOPASS && npix < (int64_t(1) << 29);
         if (!fused && precision != GABOR_PREC_FP32) {
@@ -297,6 +309,10 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
         FreqLaunch fl{};
         fl.fused = fused;
         fl.q = q;
+        // fused: read the image once, write every output once;
+        // two-pass vertical: read the J planes, write the outputs
+        fl.macs = fused ? f_row_macs + f_col_macs : f_col_macs;
+        fl.bytes = fused ? 4 * npix + 8 * f_outs : 8 * (int64_t)fjobs.size() * npix + 8 * f_outs;
         fl.in_scale = fl.mid_scale = fl.out_scale = fl.tap_scale[0] = fl.tap_scale[1] = 1.0f;
         if (fused) {
             // Strip segments at least four times the lead-in, so that the
@@ -384,7 +400,12 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
                 }
                 if (g.n_real) taps.push_back((float)s);
             }
-            for (size_t m = 0; m < members.size(); ++m) p->jobs[members[m]->job].plane = g.plane0 + (int)m;
+            int64_t gm = 0;
+            for (size_t m = 0; m < members.size(); ++m) {
+                p->jobs[members[m]->job].plane = g.plane0 + (int)m;
+                gm += (int64_t)(members[m]->real ? 1 : 2) * fd.K * npix;
+            }
+            p->row_group_macs.push_back(gm);
             p->n_planes += (int)members.size();
             p->row_groups.push_back(g);
             ci += g.n_cplx;
@@ -448,8 +469,11 @@ extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int
     if (!p->fjobs.empty() && (int64_t)(p->H - 1) * row_stride_elems + p->W >= (int64_t(1) << 30))
         return GABOR_ERR_UNSUPPORTED;   // image span past the 32-bit buffer offsets of the fused kernel
     hipStream_t stream = (hipStream_t)hip_stream;
-    for (const RowGroup& g : p->row_groups) {
-        LaunchTimer tm(p, stream, "row_fp32");
+    for (size_t gi = 0; gi < p->row_groups.size(); ++gi) {
+        const RowGroup& g = p->row_groups[gi];
+        const int64_t npix = (int64_t)p->H * p->W;
+        LaunchTimer tm(p, stream, "row_fp32_r" + std::to_string(p->freqs[g.freq].R), p->row_group_macs[gi],
+                       4 * npix + 8 * (int64_t)(g.n_cplx + g.n_real) * npix);
         if (launch_row_fp32(d_image, row_stride_elems, p->H, p->W, p->boundary, p->freqs[g.freq], g,
                             p->d_taps, p->d_J, stream) != hipSuccess)
             return GABOR_ERR_DEVICE;
@@ -466,7 +490,8 @@ extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int
         const FreqLaunch& fl = p->launches[i];
         hipStream_t ls = (j == 0 || n_aux == 0) ? stream : p->aux[(j - 1) % n_aux];
         if (fl.fused) {
-            LaunchTimer tm(p, ls, kFusedNames[p->fused_op]);
+            LaunchTimer tm(p, ls, std::string(kFusedNames[p->fused_op]) + "_r" + std::to_string(p->freqs[i].R),
+                           fl.macs, fl.bytes);
             StreamArgs sa{};
             sa.img = d_image;
             sa.stride = row_stride_elems;
@@ -488,7 +513,7 @@ extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int
             sa.tap_scale[1] = fl.tap_scale[1];
             if (launch_stream(p->fused_op, sa, fl.q, ls) != hipSuccess) return GABOR_ERR_DEVICE;
         } else {
-            LaunchTimer tm(p, ls, "col_fp32");
+            LaunchTimer tm(p, ls, "col_fp32_r" + std::to_string(p->freqs[i].R), fl.macs, fl.bytes);
             if (launch_col_fp32(p->d_J, p->H, p->W, p->boundary, p->freqs[i], p->d_jobs + fl.first,
                                 fl.count, p->d_taps, (float2*)d_out, ls) != hipSuccess)
                 return GABOR_ERR_DEVICE;
