@@ -114,6 +114,51 @@ gabor_status gabor_bank_apply(gabor_plan plan, const float* d_image,
 /* Release a plan and its device memory.  NULL is accepted (no-op). */
 gabor_status gabor_bank_destroy(gabor_plan plan);
 
+/*
+ * lsdft_apply -- Gaussian-windowed 2-D localized sliding DFT of one image
+ * (Sec. III-A, Eq. (17)-(18)), computed by the separable passes of
+ * Eq. (19)-(26) (Algorithm 2):
+ *
+ *   F_{u,v}(x,y) = sum_{j<Mx} sum_{i<My} f(x - Mx/2 + j, y - My/2 + i)
+ *                  w_x(j) w_y(i) exp(-i 2 pi (u j / Mx + v i / My))
+ *
+ * for every pixel and every bin u = 0..m_x-1, v = 0..m_y-1 (M/2 rounds down).
+ * The window is the sampled Gaussian w(j) = exp(-(M/2 - j)^2 / (2 sigma^2))
+ * over its M offsets, normalised to unit sum per axis.  Only the bins
+ * u <= Mx/2, v <= My/2 are computed; the rest follow from conjugate symmetry
+ * of the real input (Eq. (19)-(20)).  Twiddles are the FP64 values of
+ * 2 pi k / M at k = u j mod M, exact at quarter turns.
+ *
+ *   d_image           device FP32 image, height x width, row stride
+ *                     row_stride_elems (>= width).
+ *   m_y, m_x          window rows and columns, 1 .. 64 each (larger windows
+ *                     return GABOR_ERR_UNSUPPORTED).
+ *   sigma             Gaussian window scale in pixels (> 0, finite).
+ *   boundary          rule for samples outside the image.
+ *   precision         arithmetic of the contractions (as for the bank).
+ *   d_out             device complex64 output, layout [m_y][m_x][H][W]
+ *                     (plane v * m_x + u), m_y*m_x*H*W*8 bytes, fully
+ *                     overwritten.
+ *
+ * One kernel launch on hip_stream; the call allocates nothing (the window
+ * and twiddle tables travel as launch arguments), so it may be captured in
+ * a HIP graph.  Images of 2^29 pixels or more, or whose row span reaches
+ * 2^30 elements, return GABOR_ERR_UNSUPPORTED.
+ */
+gabor_status lsdft_apply(const float* d_image, int32_t height, int32_t width,
+                         int64_t row_stride_elems, int32_t m_y, int32_t m_x, double sigma,
+                         gabor_boundary boundary, gabor_precision precision, void* d_out,
+                         void* hip_stream);
+
+/*
+ * lsdft_work -- algorithmic work of one lsdft_apply (host arithmetic only):
+ * real multiply-adds counted as M taps per real 1-D pass per pixel over the
+ * computed bins, and bytes as one read of the image plus one write of every
+ * output.  Either output pointer may be NULL.
+ */
+gabor_status lsdft_work(int32_t height, int32_t width, int32_t m_y, int32_t m_x,
+                        int64_t* real_macs, int64_t* bytes);
+
 typedef struct gabor_plan_info {
     int32_t height, width, n_freq, n_orient;
     int32_t max_radius;          /* largest R over the frequencies */

@@ -6,8 +6,9 @@ current HIP stream.  There is no fallback: if libgabor.so is missing or no
 GPU is visible, calls raise.
 
 The functions keep the C names: ``gabor_bank_plan``, ``gabor_bank_apply``,
-``gabor_bank_destroy``, ``gabor_bank_plan_info``, ``gabor_status_string``.
-``GaborBank`` wraps a plan for torch tensors.
+``gabor_bank_destroy``, ``lsdft_apply``, ``lsdft_work``,
+``gabor_bank_plan_info``, ``gabor_status_string``.  ``GaborBank`` wraps a
+plan for torch tensors, ``lsdft`` wraps ``lsdft_apply``.
 """
 from __future__ import annotations
 
@@ -28,7 +29,8 @@ PRECISION = {"fp32": 0, "bf16_split": 1, "fp16_split": 2, "bf16": 3, "fp16": 4}
 
 # Every symbol include/libgabor.h declares; the CPU tests check the exports.
 EXPORTS = ["gabor_status_string", "gabor_bank_plan", "gabor_bank_apply", "gabor_bank_destroy",
-           "gabor_bank_plan_info", "gabor_profile_enable", "gabor_profile_read"]
+           "lsdft_apply", "lsdft_work", "gabor_bank_plan_info", "gabor_profile_enable",
+           "gabor_profile_read"]
 
 
 class GaborError(RuntimeError):
@@ -77,6 +79,10 @@ def load():
     lib.gabor_bank_destroy.restype = ctypes.c_int
     lib.gabor_bank_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
     lib.gabor_bank_plan_info.restype = ctypes.c_int
+    lib.lsdft_apply.argtypes = [P, i32, i32, i64, i32, i32, f64, ctypes.c_int, ctypes.c_int, P, P]
+    lib.lsdft_apply.restype = ctypes.c_int
+    lib.lsdft_work.argtypes = [i32, i32, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.lsdft_work.restype = ctypes.c_int
     lib.gabor_profile_enable.argtypes = [P, i32]
     lib.gabor_profile_enable.restype = ctypes.c_int
     lib.gabor_profile_read.argtypes = [P, ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
@@ -136,6 +142,38 @@ def gabor_bank_apply(plan, d_image: int, row_stride_elems: int, d_out: int, stre
 
 def gabor_bank_destroy(plan):
     _check(load().gabor_bank_destroy(plan), "gabor_bank_destroy")
+
+
+def lsdft_apply(d_image: int, height, width, row_stride_elems, m_y, m_x, sigma, boundary="zero",
+                precision="fp32", d_out: int = 0, stream=None):
+    st = load().lsdft_apply(ctypes.c_void_p(d_image), int(height), int(width), int(row_stride_elems),
+                            int(m_y), int(m_x), float(sigma), BOUNDARY[boundary], PRECISION[precision],
+                            ctypes.c_void_p(d_out), _stream(stream))
+    _check(st, "lsdft_apply")
+
+
+def lsdft_work(height, width, m_y, m_x) -> tuple[int, int]:
+    """(real multiply-adds, bytes) of one lsdft_apply."""
+    macs, nbytes = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().lsdft_work(int(height), int(width), int(m_y), int(m_x), ctypes.byref(macs),
+                             ctypes.byref(nbytes)), "lsdft_work")
+    return macs.value, nbytes.value
+
+
+def lsdft(img, m_y, m_x, sigma, boundary="zero", precision="fp32", out=None, stream=None):
+    """Localized SDFT of a (H, W) float32 GPU tensor (row stride may exceed
+    W): complex64 [m_y, m_x, H, W], bin (v, u) at out[v, u]."""
+    import torch
+    if img.dtype != torch.float32 or img.dim() != 2 or not img.is_cuda or img.stride(1) != 1:
+        raise ValueError("image must be a row-major 2-D float32 GPU tensor")
+    H, W = img.shape
+    if out is None:
+        out = torch.empty((m_y, m_x, H, W), dtype=torch.complex64, device=img.device)
+    elif out.dtype != torch.complex64 or not out.is_contiguous() or tuple(out.shape) != (m_y, m_x, H, W):
+        raise ValueError("out must be a contiguous complex64 [m_y, m_x, H, W] tensor")
+    lsdft_apply(img.data_ptr(), H, W, img.stride(0), m_y, m_x, sigma, boundary, precision,
+                out.data_ptr(), stream)
+    return out
 
 
 def gabor_bank_plan_info(plan) -> PlanInfo:

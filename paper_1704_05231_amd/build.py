@@ -11,13 +11,18 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgabor.so")
 
-SOURCES = ["gabor_plan.cpp", "gabor_fp32.hip", "gabor_fused.hip"]
+# (source, extra defines, object name): the fused kernel is built once per
+# arithmetic form so that its objects compile in parallel.
+SOURCES = ([("gabor_plan.cpp", [], "gabor_plan"), ("gabor_lsdft.cpp", [], "gabor_lsdft"),
+            ("gabor_fp32.hip", [], "gabor_fp32")]
+           + [("gabor_fused.hip", [f"-DGABOR_FORM={k}"], f"gabor_fused_{k}") for k in range(5)])
 ARCH = "gfx950"
 
 
@@ -47,14 +52,19 @@ def build(verbose: bool = False) -> str:
              "-I", os.path.join(ROOT, "include"), "-Wall"]
     obj_dir = os.path.join(HERE, "_build")
     os.makedirs(obj_dir, exist_ok=True)
-    for src in SOURCES:
-        obj = os.path.join(obj_dir, os.path.splitext(src)[0] + ".o")
+    cmds = []
+    for src, defs, name in SOURCES:
+        obj = os.path.join(obj_dir, name + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [hipcc()] + flags + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        _run(cmd, verbose)
+        cmds.append([hipcc()] + flags + defs + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "0") or 0) or (os.cpu_count() or 1)))
+    if verbose:
+        for cmd in cmds:
+            print(" ".join(cmd), flush=True)
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for fut in [ex.submit(_run, cmd, verbose) for cmd in cmds]:
+            fut.result()
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     _run(cmd, verbose)

@@ -215,8 +215,12 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint3
 // JR: J is real (horizontal taps have no sine part); CR: vertical taps have
 // no sine part.  Both are compile-time so that no branch separates a
 // matrix-core chain from the reads of its result.
-template <int OP, int Q, bool JR, bool CR>
-__device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob& jb, int job_rest)
+// LS: a localized SDFT job (Sec. III): the taps are formed from the window
+// weights and twiddles in lt for bins (u, v), and the job also stores
+// conj(F_a) and conj(F_b) to the planes out_c, out_d (Eq. (20)).
+template <int OP, int Q, bool JR, bool CR, bool LS>
+__device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob& jb, int job_rest,
+                                            const LsdftTaps* lt, int u, int v)
 {
     using F = Form<OP>;
     using T = typename F::T;
@@ -261,13 +265,43 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
     Pack rch[NP], rcl[NP], rdh[NP], rdl[NP], cch[NP], ccl[NP], cdh[NP], cdl[NP];
     {
         float x0v[Q], x1v[Q], x2v[Q], x3v[Q];
+        if constexpr (LS) {
+            // Localized SDFT: krev[T] = w[j] exp(-i 2 pi b j / M) at window
+            // offset j = T - (R - M/2) (Eq. (17)-(18)), b = u on the
+            // horizontal axis and v on the vertical one; the FP64 product of
+            // the window weight and the exact twiddle of index b j mod M is
+            // rounded once.  The workgroup writes the four sets to the J ring
+            // (not yet in use) and every lane reads its band from there.
+            float* tl = reinterpret_cast<float*>(stream_lds4);
+            for (int i = tid; i < 4 * KT; i += kThreads) {
+                const int set = i / KT, axis = set >> 1;
+                const int M = lt->m[axis], j = i - set * KT - 16 - (R - M / 2);
+                float val = 0.0f;
+                if (j >= 0 && j < M) {
+                    const int idx = ((axis ? v : u) * j) % M;
+                    const double wgt = lt->win[axis][j];
+                    val = (set & 1) ? (float)(-wgt * lt->tw[axis][1][idx]) : (float)(wgt * lt->tw[axis][0][idx]);
+                }
+                tl[i] = val;
+            }
+            lds_barrier();
 #pragma unroll
-        for (int e = 0; e < Q; ++e) {
-            const int m = 16 + Q * g + e - o;
-            x0v[e] = sc(tab[m], rt_s);
-            x1v[e] = sc(tab[KT + m], rt_s);
-            x2v[e] = sc(tab[2 * KT + m], ct_s);
-            x3v[e] = sc(tab[3 * KT + m], ct_s);
+            for (int e = 0; e < Q; ++e) {
+                const int m = 16 + Q * g + e - o;
+                x0v[e] = sc(tl[m], rt_s);
+                x1v[e] = sc(tl[KT + m], rt_s);
+                x2v[e] = sc(tl[2 * KT + m], ct_s);
+                x3v[e] = sc(tl[3 * KT + m], ct_s);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < Q; ++e) {
+                const int m = 16 + Q * g + e - o;
+                x0v[e] = sc(tab[m], rt_s);
+                x1v[e] = sc(tab[KT + m], rt_s);
+                x2v[e] = sc(tab[2 * KT + m], ct_s);
+                x3v[e] = sc(tab[3 * KT + m], ct_s);
+            }
         }
         F::template pack<Q>(x0v, rch, rcl);
         F::template pack<Q>(x1v, rdh, rdl);
@@ -387,6 +421,11 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
     const __amdgpu_buffer_rsrc_t out_b = jb.out_b >= 0
         ? make_rsrc(a.out + (int64_t)jb.out_b * plane, plane_bytes)
         : make_rsrc(a.out, 0u);                                 // no partner: every store dropped
+    // conjugate fill: planes that receive conj(F_a), conj(F_b)
+    const __amdgpu_buffer_rsrc_t out_c = LS && jb.out_c >= 0
+        ? make_rsrc(a.out + (int64_t)jb.out_c * plane, plane_bytes) : make_rsrc(a.out, 0u);
+    const __amdgpu_buffer_rsrc_t out_d = LS && jb.out_d >= 0
+        ? make_rsrc(a.out + (int64_t)jb.out_d * plane, plane_bytes) : make_rsrc(a.out, 0u);
     const int yend = min(a.H, yseg + a.seg_rows);
     auto col_pass = [&](int s) {
         Pack bah[NP], bal[NP], bbh[NP], bbl[NP];
@@ -429,6 +468,13 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
             vb[1] = __builtin_bit_cast(int, p3 - p4);
             __builtin_amdgcn_raw_buffer_store_b64(va, out_a, (int)off, 0, 0);
             if constexpr (!JR) __builtin_amdgcn_raw_buffer_store_b64(vb, out_b, (int)off, 0, 0);
+            if constexpr (LS) {
+                // absent planes have empty resources: their stores are dropped
+                va[1] ^= (int)0x80000000;
+                vb[1] ^= (int)0x80000000;
+                __builtin_amdgcn_raw_buffer_store_b64(va, out_c, (int)off, 0, 0);
+                if constexpr (!JR) __builtin_amdgcn_raw_buffer_store_b64(vb, out_d, (int)off, 0, 0);
+            }
         }
     };
 
@@ -485,9 +531,35 @@ __global__ __launch_bounds__(kThreads) void k_stream(StreamArgs a)
     const int rest = lid / a.n_jobs;
     // A job whose J and vertical taps are both real (omega = 0) runs the
     // real-J body with zero sine taps.
-    if (jb.j_real) stream_body<OP, Q, true, false>(a, jb, rest);
-    else if (jb.c_real) stream_body<OP, Q, false, true>(a, jb, rest);
-    else stream_body<OP, Q, false, false>(a, jb, rest);
+    if (jb.j_real) stream_body<OP, Q, true, false, false>(a, jb, rest, nullptr, 0, 0);
+    else if (jb.c_real) stream_body<OP, Q, false, true, false>(a, jb, rest, nullptr, 0, 0);
+    else stream_body<OP, Q, false, false, false>(a, jb, rest, nullptr, 0, 0);
+}
+
+// Localized SDFT (Sec. III-A): job (u, v) for u = 0..Mx/2, v = 0..My/2
+// computes J_u once (Eq. (18)), F_{u,v} and F_{Mx-u,v} from J_u and its
+// conjugate J_{Mx-u} (Eq. (19)), and stores the conjugates to F_{Mx-u,My-v}
+// and F_{u,My-v} (Eq. (20)).  Planes are indexed v Mx + u.  Bins u in
+// {0, Mx/2} have a real J_u and no partner; v in {0, My/2} real vertical
+// taps, whose conjugate outputs coincide with the direct ones.
+template <int OP, int Q>
+__global__ __launch_bounds__(kThreads) void k_lsdft(StreamArgs a, LsdftTaps t)
+{
+    const int lid = xcd_local_id(blockIdx.x, gridDim.x);
+    const int job = lid % a.n_jobs, rest = lid / a.n_jobs;
+    const int mx = t.m[0], my = t.m[1], nu = mx / 2 + 1;
+    const int u = job % nu, v = job / nu;
+    const int mu = u == 0 ? 0 : mx - u, mv = v == 0 ? 0 : my - v;
+    FusedJob jb{};
+    jb.j_real = u == mu;
+    jb.c_real = v == mv;
+    jb.out_a = v * mx + u;
+    jb.out_b = jb.j_real ? -1 : v * mx + mu;
+    jb.out_c = jb.c_real ? -1 : mv * mx + mu;
+    jb.out_d = (jb.c_real || jb.j_real) ? -1 : mv * mx + u;
+    if (jb.j_real) stream_body<OP, Q, true, false, true>(a, jb, rest, &t, u, v);
+    else if (jb.c_real) stream_body<OP, Q, false, true, true>(a, jb, rest, &t, u, v);
+    else stream_body<OP, Q, false, false, true>(a, jb, rest, &t, u, v);
 }
 
 template <int OP, int Q>
@@ -503,35 +575,66 @@ hipError_t launch_q(const StreamArgs& a, int n_blocks, hipStream_t stream)
     return hipGetLastError();
 }
 
-template <int OP>
-hipError_t launch_16(const StreamArgs& a, int Q, int n_blocks, hipStream_t stream)
+template <int OP, int Q>
+hipError_t launch_lq(const StreamArgs& a, const LsdftTaps& t, int n_blocks, hipStream_t stream)
 {
-    switch (Q) {
-        case 8: return launch_q<OP, 8>(a, n_blocks, stream);
-        case 16: return launch_q<OP, 16>(a, n_blocks, stream);
-        case 24: return launch_q<OP, 24>(a, n_blocks, stream);
-        case 32: return launch_q<OP, 32>(a, n_blocks, stream);
+    const size_t lds = stream_lds_bytes(OP, Q);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_lsdft<OP, Q>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
     }
-    return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_lsdft<OP, Q>), dim3(n_blocks), dim3(kThreads), lds, stream, a, t);
+    return hipGetLastError();
 }
 
-hipError_t launch_f32(const StreamArgs& a, int Q, int n_blocks, hipStream_t stream)
+// The quarters each form is built for: every R <= 56 for the bank, every
+// window M <= 64 (R <= 32) for the localized SDFT.
+template <int OP, int... Qs>
+hipError_t launch_bank_q(const StreamArgs& a, int Q, int n_blocks, hipStream_t stream)
 {
-    switch (Q) {
-        case 4: return launch_q<FUSED_F32, 4>(a, n_blocks, stream);
-        case 8: return launch_q<FUSED_F32, 8>(a, n_blocks, stream);
-        case 12: return launch_q<FUSED_F32, 12>(a, n_blocks, stream);
-        case 16: return launch_q<FUSED_F32, 16>(a, n_blocks, stream);
-        case 20: return launch_q<FUSED_F32, 20>(a, n_blocks, stream);
-        case 24: return launch_q<FUSED_F32, 24>(a, n_blocks, stream);
-        case 28: return launch_q<FUSED_F32, 28>(a, n_blocks, stream);
-        case 32: return launch_q<FUSED_F32, 32>(a, n_blocks, stream);
-    }
-    return hipErrorInvalidValue;
+    hipError_t e = hipErrorInvalidValue;
+    ((Q == Qs ? (void)(e = launch_q<OP, Qs>(a, n_blocks, stream)) : (void)0), ...);
+    return e;
+}
+
+template <int OP, int... Qs>
+hipError_t launch_lsdft_q(const StreamArgs& a, const LsdftTaps& t, int Q, int n_blocks, hipStream_t stream)
+{
+    hipError_t e = hipErrorInvalidValue;
+    ((Q == Qs ? (void)(e = launch_lq<OP, Qs>(a, t, n_blocks, stream)) : (void)0), ...);
+    return e;
 }
 
 }  // namespace
 
+// One object per arithmetic form: this file is compiled once per value of
+// GABOR_FORM (a FusedOp), and the form-independent host helpers go with
+// form 0.
+#ifndef GABOR_FORM
+#error "compile gabor_fused.hip with -DGABOR_FORM=<FusedOp>"
+#endif
+
+template <>
+hipError_t stream_form<GABOR_FORM>(const StreamArgs& a, int Q, int n_blocks, hipStream_t stream)
+{
+    if constexpr (GABOR_FORM == FUSED_F32)
+        return launch_bank_q<GABOR_FORM, 4, 8, 12, 16, 20, 24, 28, 32>(a, Q, n_blocks, stream);
+    else
+        return launch_bank_q<GABOR_FORM, 8, 16, 24, 32>(a, Q, n_blocks, stream);
+}
+
+template <>
+hipError_t lsdft_form<GABOR_FORM>(const StreamArgs& a, const LsdftTaps& t, int Q, int n_blocks,
+                                  hipStream_t stream)
+{
+    if constexpr (GABOR_FORM == FUSED_F32)
+        return launch_lsdft_q<GABOR_FORM, 4, 8, 12, 16, 20>(a, t, Q, n_blocks, stream);
+    else
+        return launch_lsdft_q<GABOR_FORM, 8, 16, 24>(a, t, Q, n_blocks, stream);
+}
+
+#if GABOR_FORM == 0
 int stream_quarter(int op, int R)
 {
     const int need = 16 + 2 * R;                         // inputs per 16-block
@@ -552,6 +655,25 @@ size_t stream_lds_bytes(int op, int Q)
 
 int stream_strip_width() { return kSX; }
 
+hipError_t launch_lsdft(int op, const StreamArgs& a, const LsdftTaps& t, int Q, hipStream_t stream)
+{
+    if (t.m[0] < 1 || t.m[0] > kLsdftMaxM || t.m[1] < 1 || t.m[1] > kLsdftMaxM) return hipErrorInvalidValue;
+    if (a.n_jobs != (t.m[0] / 2 + 1) * (t.m[1] / 2 + 1) || 2 * a.R < t.m[0] - 1 || 2 * a.R < t.m[1] - 1)
+        return hipErrorInvalidValue;
+    if (a.seg_rows <= 0 || a.seg_rows % 16 != 0 || 16 + 2 * a.R > 4 * Q || Q > kStreamMaxQuarter)
+        return hipErrorInvalidValue;
+    const long long nb = (long long)a.n_xs * a.n_ys * a.n_jobs;
+    if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    switch (op) {
+        case FUSED_F32: return lsdft_form<FUSED_F32>(a, t, Q, (int)nb, stream);
+        case FUSED_BF16: return lsdft_form<FUSED_BF16>(a, t, Q, (int)nb, stream);
+        case FUSED_BF16X3: return lsdft_form<FUSED_BF16X3>(a, t, Q, (int)nb, stream);
+        case FUSED_F16: return lsdft_form<FUSED_F16>(a, t, Q, (int)nb, stream);
+        case FUSED_F16X3: return lsdft_form<FUSED_F16X3>(a, t, Q, (int)nb, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_stream(int op, const StreamArgs& a, int Q, hipStream_t stream)
 {
     if (a.n_jobs <= 0) return hipSuccess;
@@ -560,13 +682,14 @@ hipError_t launch_stream(int op, const StreamArgs& a, int Q, hipStream_t stream)
     const long long nb = (long long)a.n_xs * a.n_ys * a.n_jobs;
     if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidValue;
     switch (op) {
-        case FUSED_F32: return launch_f32(a, Q, (int)nb, stream);
-        case FUSED_BF16: return launch_16<FUSED_BF16>(a, Q, (int)nb, stream);
-        case FUSED_BF16X3: return launch_16<FUSED_BF16X3>(a, Q, (int)nb, stream);
-        case FUSED_F16: return launch_16<FUSED_F16>(a, Q, (int)nb, stream);
-        case FUSED_F16X3: return launch_16<FUSED_F16X3>(a, Q, (int)nb, stream);
+        case FUSED_F32: return stream_form<FUSED_F32>(a, Q, (int)nb, stream);
+        case FUSED_BF16: return stream_form<FUSED_BF16>(a, Q, (int)nb, stream);
+        case FUSED_BF16X3: return stream_form<FUSED_BF16X3>(a, Q, (int)nb, stream);
+        case FUSED_F16: return stream_form<FUSED_F16>(a, Q, (int)nb, stream);
+        case FUSED_F16X3: return stream_form<FUSED_F16X3>(a, Q, (int)nb, stream);
     }
     return hipErrorInvalidValue;
 }
+#endif
 
 }  // namespace gabor

@@ -47,12 +47,14 @@ enum FusedOp { FUSED_F32 = 0, FUSED_BF16 = 1, FUSED_BF16X3 = 2, FUSED_F16 = 3, F
 constexpr int kStreamMaxQuarter = 32;   // contracted length L = 4Q <= 128: R <= 56
 
 struct FusedJob {
-    int32_t out_a;     // output channel i*N + n
-    int32_t out_b;     // pi - theta partner channel or -1
-    int32_t j_real;    // horizontal taps have no sine part (w cos(theta) == 0)
-    int32_t c_real;    // vertical taps have no sine part (w sin(theta) == 0)
+    int32_t out_a;     // output plane of F = J * k
+    int32_t out_b;     // output plane of conj(J) * k (pi - theta, or M - u) or -1
+    int32_t out_c;     // plane that receives conj(F_a) or -1 (conjugate fill)
+    int32_t out_d;     // plane that receives conj(F_b) or -1
+    int32_t j_real;    // horizontal taps have no sine part
+    int32_t c_real;    // vertical taps have no sine part
     int32_t tap_off;   // [4][L+16] zero-padded reversed taps: row c, row d, col c, col d
-    int32_t pad_[3];
+    int32_t pad_;
 };
 
 struct StreamArgs {
@@ -70,10 +72,35 @@ struct StreamArgs {
     float tap_scale[2];        // horizontal, vertical tap scales
 };
 
+// Localized SDFT taps, passed by value as a kernel argument (no device
+// tables): axis 0 is x (the horizontal pass), axis 1 is y.
+constexpr int kLsdftMaxM = 64;
+struct LsdftTaps {
+    int32_t m[2];                      // window size Mx, My
+    double win[2][kLsdftMaxM];         // Gaussian window weights of offsets j = 0..M-1, unit sum
+    double tw[2][2][kLsdftMaxM];       // cos, sin of 2 pi k / M, k = 0..M-1 (exact at quarter turns)
+};
+
 int stream_quarter(int op, int R);             // Q for radius R (L = 4Q >= 16 + 2R)
 size_t stream_lds_bytes(int op, int Q);
 int stream_strip_width();
 hipError_t launch_stream(int op, const StreamArgs& a, int Q, hipStream_t stream);
+hipError_t launch_lsdft(int op, const StreamArgs& a, const LsdftTaps& t, int Q, hipStream_t stream);
+
+// Per-form launchers (one object per form); Q outside the built set returns
+// hipErrorInvalidValue.
+template <int OP> hipError_t stream_form(const StreamArgs& a, int Q, int n_blocks, hipStream_t stream);
+template <int OP> hipError_t lsdft_form(const StreamArgs& a, const LsdftTaps& t, int Q, int n_blocks,
+                                        hipStream_t stream);
+#define GABOR_DECLARE_FORM(OP)                                                                   \
+    template <> hipError_t stream_form<OP>(const StreamArgs&, int, int, hipStream_t);            \
+    template <> hipError_t lsdft_form<OP>(const StreamArgs&, const LsdftTaps&, int, int, hipStream_t);
+GABOR_DECLARE_FORM(FUSED_F32)
+GABOR_DECLARE_FORM(FUSED_BF16)
+GABOR_DECLARE_FORM(FUSED_BF16X3)
+GABOR_DECLARE_FORM(FUSED_F16)
+GABOR_DECLARE_FORM(FUSED_F16X3)
+#undef GABOR_DECLARE_FORM
 
 // Launchers (defined in gabor_fp32.hip).  They return the status of the
 // launch (hipGetLastError after enqueue).

@@ -338,6 +338,7 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
                 FusedJob f{};
                 f.out_a = fjobs[j].out_a;
                 f.out_b = fjobs[j].out_b;
+                f.out_c = f.out_d = -1;
                 f.j_real = fjobs[j].j_real;
                 f.c_real = fjobs[j].c_real;
                 f.tap_off = (int)taps.size();

@@ -86,3 +86,44 @@ def test_forced_allocation_failure(monkeypatch):
 def test_oversized_radius_is_unsupported():
     st, _ = _plan_raw(sg=(5000.0,))
     assert st == 4
+
+
+def _lsdft_raw(img=16, H=8, W=8, stride=8, my=4, mx=4, sigma=1.0, bnd=0, prec=0, out=16):
+    lib = binding.load()
+    return lib.lsdft_apply(None if img is None else ctypes.c_void_p(img), H, W, stride, my, mx,
+                           sigma, bnd, prec, None if out is None else ctypes.c_void_p(out), None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(img=None), dict(out=None), dict(H=0), dict(W=-1), dict(stride=7), dict(my=0),
+    dict(mx=-2), dict(sigma=0.0), dict(sigma=float("nan")), dict(sigma=-1.0), dict(bnd=2),
+    dict(prec=5),
+])
+def test_lsdft_rejects_bad_arguments(kw):
+    # rejected on the host: the fake device pointers are never touched
+    assert _lsdft_raw(**kw) == 1
+
+
+@pytest.mark.parametrize("kw", [dict(my=65), dict(mx=100), dict(H=1 << 15, W=1 << 14, stride=1 << 14),
+                                dict(H=40000, W=2, stride=1 << 15)])
+def test_lsdft_limits_are_unsupported(kw):
+    assert _lsdft_raw(**kw) == 4
+
+
+def test_lsdft_work_counts():
+    """Bins u <= Mx/2, v <= My/2 (Eq. (19)-(20)); a pass over a complex
+    operand costs two real products per tap, a real one one."""
+    def count(my, mx):
+        macs = 0
+        for u in range(mx // 2 + 1):
+            ju = 1 if (2 * u) % mx == 0 else 2
+            macs += ju * mx
+            for v in range(my // 2 + 1):
+                cv = 1 if (2 * v) % my == 0 else 2
+                macs += ju * cv * my
+        return macs
+    for (H, W, my, mx) in [(512, 512, 16, 16), (7, 9, 5, 12), (3, 4, 1, 1), (10, 10, 2, 7)]:
+        macs, nbytes = binding.lsdft_work(H, W, my, mx)
+        assert macs == count(my, mx) * H * W
+        assert nbytes == 4 * H * W + 8 * my * mx * H * W
+    assert binding.load().lsdft_work(0, 4, 4, 4, None, None) == 1

@@ -1,0 +1,127 @@
+"""GPU parity of the localized sliding DFT (Sec. III-A, Eq. (17)-(18))
+through lsdft_apply against the FP64 oracle.
+
+Error measure (per bin): max over pixels of |F_gpu - F_ref| divided by max
+over pixels of |F_ref|.  Bars as for the bank: 1e-5 for FP32 and the
+float16 hi/lo split, 1e-3 for the bfloat16 hi/lo split, and 8 u max|f| /
+peak for single 16-bit products (|F| <= max|f| because the window weights
+sum to one on each axis).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1704_05231_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOLS = {"fp32": 1e-5, "fp16_split": 1e-5, "bf16_split": 1e-3}
+UNIT = {"bf16": 2.0 ** -9, "fp16": 2.0 ** -12}
+PRECISIONS = ["fp32", "fp16_split", "bf16_split", "fp16", "bf16"]
+
+
+def gpu_lsdft(binding, img, my, mx, sigma, boundary="zero", precision="fp32", stride_pad=0):
+    import torch
+    H, W = img.shape
+    buf = torch.zeros((H, W + stride_pad), dtype=torch.float32, device="cuda")
+    buf[:, :W] = torch.from_numpy(img).cuda()
+    # poison the output: every plane must be overwritten
+    out = torch.full((my, mx, H, W), float("nan"), dtype=torch.complex64, device="cuda")
+    binding.lsdft(buf[:, :W], my, mx, sigma, boundary, precision, out=out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def per_bin_err(got, ref, axis_pts):
+    """Peak-relative error per bin; axis_pts are the pixel axes."""
+    num = np.abs(got - ref).max(axis=axis_pts)
+    den = np.abs(ref).max(axis=axis_pts)
+    return num / np.maximum(den, 1e-300), den
+
+
+def tol(prec, img, peak):
+    if prec in TOLS:
+        return TOLS[prec]
+    return 8 * UNIT[prec] * np.abs(img).max() / peak
+
+
+CASES = [
+    # (H, W, My, Mx, sigma, boundary)
+    (70, 150, 8, 8, 2.0, "zero"),         # several strips, ragged tail, even M
+    (70, 150, 8, 8, 2.0, "mirror"),
+    (45, 77, 7, 7, 1.5, "zero"),          # odd M: no real middle bin
+    (45, 77, 12, 6, 2.0, "mirror"),       # My != Mx
+    (33, 40, 5, 10, 3.0, "zero"),         # My < Mx
+    (20, 19, 1, 1, 1.0, "mirror"),        # one bin: the window weight is 1
+    (20, 19, 2, 2, 0.7, "zero"),          # u, v in {0, M/2} only
+    (1, 90, 4, 6, 1.0, "mirror"),         # one row
+    (90, 1, 6, 4, 1.0, "zero"),           # one column
+    (150, 140, 16, 16, 4.0, "mirror"),    # the window of the 512^2 workload
+]
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_lsdft_full_grid(gpu_lib, case, prec):
+    H, W, my, mx, sg, bnd = CASES[case]
+    img = workloads.uniform_image(H, W, 300 + case)
+    got = gpu_lsdft(gpu_lib, img, my, mx, sg, bnd, prec)
+    ref = oracle.lsdft(img, my, mx, sg, bnd)
+    assert np.all(np.isfinite(got)), "a bin plane was not written"
+    err, peak = per_bin_err(got, ref, (2, 3))
+    print(f"lsdft case {case} {H}x{W} {my}x{mx} {bnd} {prec}: max per-bin rel err {err.max():.3e}")
+    assert np.all(err <= tol(prec, img, peak))
+
+
+def test_lsdft_conjugate_bins_bitwise(gpu_lib):
+    """F_{Mx-u, My-v} = conj(F_{u,v}) for a real image (Eq. (20)): the
+    kernel stores the conjugate of the very same values."""
+    img = workloads.uniform_image(40, 70, 11)
+    my, mx = 10, 6
+    F = gpu_lsdft(gpu_lib, img, my, mx, 2.0, "mirror")
+    for v in range(my):
+        for u in range(mx):
+            np.testing.assert_array_equal(F[(my - v) % my, (mx - u) % mx], np.conj(F[v, u]))
+
+
+def test_lsdft_row_stride(gpu_lib):
+    img = workloads.uniform_image(50, 66, 12)
+    a = gpu_lsdft(gpu_lib, img, 8, 8, 2.0, "mirror")
+    b = gpu_lsdft(gpu_lib, img, 8, 8, 2.0, "mirror", stride_pad=9)
+    np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("m", [(64, 64), (64, 3), (33, 64)])
+def test_lsdft_largest_windows_sampled(gpu_lib, m):
+    """Largest windows the library takes (M = 64), checked at sampled pixels."""
+    my, mx = m
+    H, W = 150, 170
+    img = workloads.uniform_image(H, W, 13)
+    xs, ys = workloads.sample_pixels(H, W, 40, 14)
+    ref = oracle.lsdft_points(img, my, mx, 10.0, xs, ys, "mirror")      # [P, My, Mx]
+    for prec in ["fp32", "bf16_split"]:
+        got = gpu_lsdft(gpu_lib, img, my, mx, 10.0, "mirror", prec)[:, :, ys, xs].transpose(2, 0, 1)
+        err, peak = per_bin_err(got, ref, 0)
+        print(f"lsdft {my}x{mx} {prec}: sampled max per-bin rel err {err.max():.3e}")
+        assert np.all(err <= tol(prec, img, peak))
+
+
+@pytest.fixture(scope="module")
+def lsdft_512_ref():
+    wl = workloads.lsdft_512()
+    xs, ys = workloads.sample_pixels(512, 512, 1500, 15)
+    ref = oracle.lsdft_points(wl.image, wl.my, wl.mx, wl.sigma, xs, ys, wl.boundary)
+    return wl, xs, ys, ref
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_lsdft_512_sampled(gpu_lib, lsdft_512_ref, prec):
+    """The 512^2, 16 x 16 window, sigma = 4 workload (all 256 bins) in its
+    benchmark launch, checked at sampled pixels (corners included)."""
+    wl, xs, ys, ref = lsdft_512_ref
+    got = gpu_lsdft(gpu_lib, wl.image, wl.my, wl.mx, wl.sigma, wl.boundary, prec)
+    assert np.all(np.isfinite(got))
+    g = got[:, :, ys, xs].transpose(2, 0, 1)
+    err, peak = per_bin_err(g, ref, 0)
+    print(f"lsdft-512 {prec}: sampled max per-bin rel err {err.max():.3e}")
+    assert np.all(err <= tol(prec, wl.image, peak))
