@@ -111,6 +111,30 @@ gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t width,
 gabor_status gabor_bank_apply(gabor_plan plan, const float* d_image,
                               int64_t row_stride_elems, void* d_out, void* hip_stream);
 
+/*
+ * gabor_bank_apply_adjoint -- gradient of a real loss L with respect to the
+ * image, given its gradient with respect to every bank output (the adjoint
+ * of gabor_bank_apply; derived from Eq. (1)).
+ *
+ *   d_grad_out        device complex64 [O][N][H][W], the plan's output
+ *                     layout; element c holds dL/dRe F_c + i dL/dIm F_c (the
+ *                     convention of PyTorch's complex gradients).
+ *   d_grad_image      device FP32 [H][W] with row stride
+ *                     grad_row_stride_elems (>= width), fully overwritten with
+ *                       dL/df(q) = sum_c sum_p Re(conj(G_c(p)) K_c(p - q)),
+ *                     i.e. sum_c Re((G_c * K_c)(q)): the Gabor kernel is
+ *                     Hermitian, so the adjoint is the same bank applied to
+ *                     the complex gradients, real part summed over channels.
+ *
+ * Only plans with GABOR_BOUNDARY_ZERO are supported (a mirror plan returns
+ * GABOR_ERR_UNSUPPORTED).  The arithmetic is FP32 whatever the plan's
+ * precision.  The first call on a plan allocates its adjoint workspace (one
+ * complex plane per horizontal pass), which the plan keeps until destroyed;
+ * later calls allocate nothing.
+ */
+gabor_status gabor_bank_apply_adjoint(gabor_plan plan, const void* d_grad_out, float* d_grad_image,
+                                      int64_t grad_row_stride_elems, void* hip_stream);
+
 /* Release a plan and its device memory.  NULL is accepted (no-op). */
 gabor_status gabor_bank_destroy(gabor_plan plan);
 

@@ -28,8 +28,8 @@ BOUNDARY = {"zero": 0, "mirror": 1}
 PRECISION = {"fp32": 0, "bf16_split": 1, "fp16_split": 2, "bf16": 3, "fp16": 4}
 
 # Every symbol include/libgabor.h declares; the CPU tests check the exports.
-EXPORTS = ["gabor_status_string", "gabor_bank_plan", "gabor_bank_apply", "gabor_bank_destroy",
-           "lsdft_apply", "lsdft_work", "gabor_bank_plan_info", "gabor_profile_enable",
+EXPORTS = ["gabor_status_string", "gabor_bank_plan", "gabor_bank_apply", "gabor_bank_apply_adjoint",
+           "gabor_bank_destroy", "lsdft_apply", "lsdft_work", "gabor_bank_plan_info", "gabor_profile_enable",
            "gabor_profile_read"]
 
 
@@ -75,6 +75,8 @@ def load():
     lib.gabor_bank_plan.restype = ctypes.c_int
     lib.gabor_bank_apply.argtypes = [P, P, i64, P, P]
     lib.gabor_bank_apply.restype = ctypes.c_int
+    lib.gabor_bank_apply_adjoint.argtypes = [P, P, P, i64, P]
+    lib.gabor_bank_apply_adjoint.restype = ctypes.c_int
     lib.gabor_bank_destroy.argtypes = [P]
     lib.gabor_bank_destroy.restype = ctypes.c_int
     lib.gabor_bank_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
@@ -138,6 +140,13 @@ def gabor_bank_apply(plan, d_image: int, row_stride_elems: int, d_out: int, stre
     st = load().gabor_bank_apply(plan, ctypes.c_void_p(d_image), int(row_stride_elems),
                                  ctypes.c_void_p(d_out), _stream(stream))
     _check(st, "gabor_bank_apply")
+
+
+def gabor_bank_apply_adjoint(plan, d_grad_out: int, d_grad_image: int, grad_row_stride_elems: int,
+                             stream=None):
+    st = load().gabor_bank_apply_adjoint(plan, ctypes.c_void_p(d_grad_out), ctypes.c_void_p(d_grad_image),
+                                         int(grad_row_stride_elems), _stream(stream))
+    _check(st, "gabor_bank_apply_adjoint")
 
 
 def gabor_bank_destroy(plan):
@@ -235,6 +244,21 @@ class GaborBank:
             raise ValueError("out must be a contiguous complex64 [O, N, H, W] tensor")
         gabor_bank_apply(self._plan, img.data_ptr(), img.stride(0), out.data_ptr(), stream)
         return out
+
+    def adjoint(self, grad_out, grad_img=None, stream=None):
+        """dL/df (float32 [H, W]) from dL/dF (complex64 [O, N, H, W])."""
+        import torch
+        if (grad_out.dtype != torch.complex64 or not grad_out.is_contiguous() or not grad_out.is_cuda
+                or tuple(grad_out.shape) != (self.n_freq, self.n_orient, self.height, self.width)):
+            raise ValueError("grad_out must be a contiguous complex64 [O, N, H, W] GPU tensor")
+        if grad_img is None:
+            grad_img = torch.empty((self.height, self.width), dtype=torch.float32, device=grad_out.device)
+        elif (grad_img.dtype != torch.float32 or grad_img.dim() != 2 or grad_img.stride(1) != 1
+              or tuple(grad_img.shape) != (self.height, self.width)):
+            raise ValueError("grad_img must be a row-major float32 [H, W] tensor")
+        gabor_bank_apply_adjoint(self._plan, grad_out.data_ptr(), grad_img.data_ptr(), grad_img.stride(0),
+                                 stream)
+        return grad_img
 
     def profile(self, enable: bool = True):
         gabor_profile_enable(self._plan, enable)

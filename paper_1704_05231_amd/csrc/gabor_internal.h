@@ -102,6 +102,26 @@ GABOR_DECLARE_FORM(FUSED_F16)
 GABOR_DECLARE_FORM(FUSED_F16X3)
 #undef GABOR_DECLARE_FORM
 
+// One horizontal result of the bank as seen by the adjoint (zero boundary):
+// the channels it feeds and its tap sets.
+struct AdjJob {
+    int32_t R, Kp;     // radius and padded tap count of its frequency
+    int32_t out_a;     // channel i*N + n
+    int32_t out_b;     // pi - theta partner channel or -1
+    int32_t j_real;    // horizontal taps have no sine part
+    int32_t c_real;    // vertical taps have no sine part
+    int32_t tap_off;   // [4][Kp] reversed taps k(R - T): row c, row d, col c, col d
+    int32_t pad_;
+};
+
+size_t adj_row_lds_bytes(int max_kp);
+size_t adj_col_lds_bytes(int max_kp);
+// Horizontal adjoint pass of every job into d_J ([n_jobs][H][W]), then the
+// vertical pass summed over the jobs into d_grad (gabor_adjoint.hip).
+hipError_t launch_adjoint(const float2* d_G, int H, int W, const AdjJob* d_jobs, int n_jobs, int max_kp,
+                          const float* d_taps, float2* d_J, float* d_grad, int64_t grad_stride,
+                          hipStream_t stream);
+
 // Launchers (defined in gabor_fp32.hip).  They return the status of the
 // launch (hipGetLastError after enqueue).
 hipError_t launch_row_fp32(const float* img, int64_t stride, int H, int W, int boundary,

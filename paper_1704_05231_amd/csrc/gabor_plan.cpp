@@ -50,6 +50,11 @@ struct gabor_plan_s {
     std::vector<FusedJob> fjobs;           // fused jobs
     std::vector<FreqLaunch> launches;      // per frequency
     std::vector<int> order;                // launch order of the frequencies
+    std::vector<AdjJob> ajobs;             // adjoint jobs (every horizontal result)
+    int adj_max_kp = 0;
+    int64_t adj_row_macs = 0, adj_col_macs = 0;
+    AdjJob* d_ajobs = nullptr;
+    float2* d_adjJ = nullptr;              // adjoint workspace, allocated by the first adjoint call
     int fused_op = FUSED_F32;
     int32_t n_planes = 0;
     int32_t n_row_passes = 0, n_col_passes = 0;
@@ -111,6 +116,8 @@ void release(gabor_plan p)
     if (p->d_jobs) (void)hipFree(p->d_jobs);
     if (p->d_fjobs) (void)hipFree(p->d_fjobs);
     if (p->d_J) (void)hipFree(p->d_J);
+    if (p->d_ajobs) (void)hipFree(p->d_ajobs);
+    if (p->d_adjJ) (void)hipFree(p->d_adjJ);
     for (hipStream_t st : p->aux) (void)hipStreamDestroy(st);
     for (hipEvent_t e : p->fork_ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : p->join_ev) (void)hipEventDestroy(e);
@@ -292,6 +299,32 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
             fws.push_back(ws);
         }
 
+        // Adjoint jobs: reversed taps k(R - T) of both passes, zero-padded to Kp.
+        for (size_t j = 0; j < fjobs.size(); ++j) {
+            AdjJob aj{};
+            aj.R = fd.R;
+            aj.Kp = fd.Kp;
+            aj.out_a = fjobs[j].out_a;
+            aj.out_b = fjobs[j].out_b;
+            aj.j_real = fjobs[j].j_real;
+            aj.c_real = fjobs[j].c_real;
+            aj.tap_off = (int)taps.size();
+            const double w4[4] = {fwc[j], fwc[j], fws[j], fws[j]};
+            for (int set = 0; set < 4; ++set)
+                for (int T = 0; T < fd.Kp; ++T) {
+                    double v = 0.0;
+                    if (T < fd.K) {
+                        const int t = fd.R - T;
+                        v = S[T] * ((set & 1) ? std::sin(w4[set] * t) : std::cos(w4[set] * t));
+                    }
+                    taps.push_back((float)v);
+                }
+            p->ajobs.push_back(aj);
+            p->adj_max_kp = std::max(p->adj_max_kp, fd.Kp);
+            p->adj_row_macs += (int64_t)(aj.j_real ? 2 : 4) * fd.K * npix;
+            p->adj_col_macs += (int64_t)(aj.c_real ? 1 : 2) * fd.K * npix;
+        }
+
         // The fused kernel addresses the image and each output plane through
         // 32-bit buffer offsets: planes of at most 2^29 pixels.
         int64_t f_row_macs = 0, f_col_macs = 0, f_outs = 0;
@@ -319,6 +352,10 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
             // lead-in recomputation stays under a quarter of the J rows.
             const int L = 4 * q;
             fl.seg_rows = std::max(128, 4 * L);
+            if (const char* sr = std::getenv("LIBGABOR_SEG_ROWS")) {
+                const int v = std::atoi(sr);
+                if (v >= 16) fl.seg_rows = v / 16 * 16;
+            }
             if (fl.seg_rows > height) fl.seg_rows = (height + 15) / 16 * 16;
             if (p->fused_op == FUSED_F16 || p->fused_op == FUSED_F16X3) {
                 // float16 range: image scaled by 2^8 (|f| <= 128 stays below
@@ -422,8 +459,9 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
     const size_t taps_bytes = taps.size() * sizeof(float);
     const size_t jobs_bytes = p->jobs.size() * sizeof(ColJob);
     const size_t fjobs_bytes = p->fjobs.size() * sizeof(FusedJob);
+    const size_t ajobs_bytes = p->ajobs.size() * sizeof(AdjJob);
     const size_t J_bytes = (size_t)p->n_planes * (size_t)npix * sizeof(float2);
-    p->workspace_bytes = (int64_t)(taps_bytes + jobs_bytes + fjobs_bytes + J_bytes);
+    p->workspace_bytes = (int64_t)(taps_bytes + jobs_bytes + fjobs_bytes + ajobs_bytes + J_bytes);
     if (env_flag("LIBGABOR_FAIL_ALLOC")) {
         release(p);
         return GABOR_ERR_OUT_OF_MEMORY;
@@ -434,6 +472,7 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
     if (e == hipSuccess && jobs_bytes) e = hipMalloc((void**)&p->d_jobs, jobs_bytes);
     if (e == hipSuccess && fjobs_bytes) e = hipMalloc((void**)&p->d_fjobs, fjobs_bytes);
     if (e == hipSuccess && J_bytes) e = hipMalloc((void**)&p->d_J, J_bytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_ajobs, ajobs_bytes);
     if (e != hipSuccess) {
         release(p);
         return e == hipErrorOutOfMemory ? GABOR_ERR_OUT_OF_MEMORY : GABOR_ERR_DEVICE;
@@ -441,6 +480,7 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
     if (hipMemcpyAsync(p->d_taps, taps.data(), taps_bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
         (jobs_bytes && hipMemcpyAsync(p->d_jobs, p->jobs.data(), jobs_bytes, hipMemcpyHostToDevice, stream) != hipSuccess) ||
         (fjobs_bytes && hipMemcpyAsync(p->d_fjobs, p->fjobs.data(), fjobs_bytes, hipMemcpyHostToDevice, stream) != hipSuccess) ||
+        hipMemcpyAsync(p->d_ajobs, p->ajobs.data(), ajobs_bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess) {
         release(p);
         return GABOR_ERR_DEVICE;
@@ -526,6 +566,34 @@ extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int
             return GABOR_ERR_DEVICE;
     }
     return GABOR_OK;
+}
+
+extern "C" gabor_status gabor_bank_apply_adjoint(gabor_plan p, const void* d_grad_out, float* d_grad_image,
+                                                 int64_t grad_row_stride_elems, void* hip_stream)
+{
+    if (!p || !d_grad_out || !d_grad_image) return GABOR_ERR_INVALID_ARG;
+    if (grad_row_stride_elems < p->W) return GABOR_ERR_INVALID_ARG;
+    if (p->boundary != GABOR_BOUNDARY_ZERO) return GABOR_ERR_UNSUPPORTED;
+    if (adj_row_lds_bytes(p->adj_max_kp) > 160 * 1024 || adj_col_lds_bytes(p->adj_max_kp) > 160 * 1024)
+        return GABOR_ERR_UNSUPPORTED;
+    const int64_t npix = (int64_t)p->H * p->W;
+    if (!p->d_adjJ) {
+        const size_t bytes = p->ajobs.size() * (size_t)npix * sizeof(float2);
+        if (env_flag("LIBGABOR_FAIL_ALLOC")) return GABOR_ERR_OUT_OF_MEMORY;
+        const hipError_t e = hipMalloc((void**)&p->d_adjJ, bytes);
+        if (e != hipSuccess) {
+            p->d_adjJ = nullptr;
+            return e == hipErrorOutOfMemory ? GABOR_ERR_OUT_OF_MEMORY : GABOR_ERR_DEVICE;
+        }
+        p->workspace_bytes += (int64_t)bytes;
+    }
+    hipStream_t stream = (hipStream_t)hip_stream;
+    LaunchTimer tm(p, stream, "adjoint_fp32", p->adj_row_macs + p->adj_col_macs,
+                   8 * (int64_t)p->O * p->N * npix + 4 * npix);
+    return launch_adjoint((const float2*)d_grad_out, p->H, p->W, p->d_ajobs, (int)p->ajobs.size(), p->adj_max_kp,
+                          p->d_taps, p->d_adjJ, d_grad_image, grad_row_stride_elems, stream) == hipSuccess
+               ? GABOR_OK
+               : GABOR_ERR_DEVICE;
 }
 
 extern "C" gabor_status gabor_bank_destroy(gabor_plan p)

@@ -127,3 +127,8 @@ def test_lsdft_work_counts():
         assert macs == count(my, mx) * H * W
         assert nbytes == 4 * H * W + 8 * my * mx * H * W
     assert binding.load().lsdft_work(0, 4, 4, 4, None, None) == 1
+
+
+def test_adjoint_rejects_null_arguments():
+    lib = binding.load()
+    assert lib.gabor_bank_apply_adjoint(None, ctypes.c_void_p(16), ctypes.c_void_p(16), 8, None) == 1

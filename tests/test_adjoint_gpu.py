@@ -1,0 +1,159 @@
+"""GPU checks of the hand-written adjoint (gabor_bank_apply_adjoint) and the
+autograd layer built on it (zero boundary, FP32).
+
+1. Dot-product identity: <bank(f), G> = <f, adjoint(G)> for random f and G,
+   with <F, G> = sum Re(conj(G) F), both sides summed in FP64.
+2. The oracle's FP64 gradient of L = mean |F|^2 at sampled pixels.
+3. Central finite differences of the same loss (h = 1e-3) at sampled pixels,
+   each difference formed as an FP64 sum over the outputs within R of the
+   pixel, from two GPU forwards of the perturbed image (a difference of two
+   whole-loss FP32 scalars would cancel below FP32 resolution).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1704_05231_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+BANKS = [
+    # (H, W, omegas, sigmas, N, thetas)
+    (64, 80, [math.pi / 4, math.pi / 8], [2.0, 3.0], 8, None),
+    (37, 53, [1.3, 0.5], [1.5, 2.5], 5, None),                       # odd N: unpaired orientations
+    (48, 40, [1.1], [2.2], 5, [0.0, 0.4, math.pi - 0.4, 1.0, math.pi / 2]),
+    (20, 90, [0.0, 2.0], [3.0, 1.0], 3, None),                       # omega = 0
+    (130, 70, [math.pi / 16], [16.0], 8, None),                      # R = 48 > half the width
+]
+
+
+def make_bank(gpu_lib, H, W, om, sg, N, th):
+    return gpu_lib.GaborBank(H, W, om, sg, N, th, 3.0, "zero", "fp32")
+
+
+@pytest.mark.parametrize("case", range(len(BANKS)))
+def test_adjoint_dot_product_identity(gpu_lib, case):
+    import torch
+    H, W, om, sg, N, th = BANKS[case]
+    bank = make_bank(gpu_lib, H, W, om, sg, N, th)
+    rng = np.random.Generator(np.random.PCG64(500 + case))
+    f = rng.uniform(-1, 1, (H, W)).astype(np.float32)
+    G = (rng.uniform(-1, 1, (len(om), N, H, W)) + 1j * rng.uniform(-1, 1, (len(om), N, H, W))).astype(np.complex64)
+    F = bank(torch.from_numpy(f).cuda()).cpu().numpy()
+    g = bank.adjoint(torch.from_numpy(G).cuda()).cpu().numpy()
+    bank.close()
+    lhs = np.sum((np.conj(G.astype(np.complex128)) * F.astype(np.complex128)).real)
+    rhs = np.sum(f.astype(np.float64) * g.astype(np.float64))
+    scale = np.sum(np.abs(G) * np.abs(F))
+    print(f"adjoint case {case}: <Ff,G> = {lhs:.9e}, <f,A G> = {rhs:.9e}, rel {abs(lhs - rhs) / scale:.2e}")
+    assert abs(lhs - rhs) <= 1e-6 * scale
+
+
+def test_adjoint_row_stride_and_overwrite(gpu_lib):
+    import torch
+    H, W, om, sg, N, th = BANKS[0]
+    bank = make_bank(gpu_lib, H, W, om, sg, N, th)
+    rng = np.random.Generator(np.random.PCG64(510))
+    G = torch.from_numpy((rng.uniform(-1, 1, (2, N, H, W)) + 1j * rng.uniform(-1, 1, (2, N, H, W)))
+                         .astype(np.complex64)).cuda()
+    a = bank.adjoint(G)
+    buf = torch.full((H, W + 7), float("nan"), device="cuda")
+    b = bank.adjoint(G, buf[:, :W])
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.isnan(buf[:, W:]).all()          # padding columns untouched
+    bank.close()
+
+
+def test_adjoint_mirror_plan_is_unsupported(gpu_lib):
+    import torch
+    bank = gpu_lib.GaborBank(16, 16, [1.0], [2.0], 4, None, 3.0, "mirror", "fp32")
+    G = torch.zeros((1, 4, 16, 16), dtype=torch.complex64, device="cuda")
+    with pytest.raises(gpu_lib.GaborError) as ei:
+        bank.adjoint(G)
+    assert ei.value.status == 4
+    bank.close()
+
+
+def loss_grad_gpu(gpu_lib, img, om, sg, N, th):
+    """Autograd gradient of L = mean |F|^2 through the layer."""
+    import torch
+    from paper_1704_05231_amd.autograd import GaborLayer
+    H, W = img.shape
+    layer = GaborLayer(H, W, om, sg, N, th)
+    x = torch.from_numpy(img).cuda().requires_grad_(True)
+    F = layer(x)
+    loss = (F.real ** 2 + F.imag ** 2).mean()
+    loss.backward()
+    g = x.grad.cpu().numpy()
+    layer.close()
+    return g
+
+
+@pytest.mark.parametrize("case", [0, 1, 3, 4])
+def test_autograd_gradient_matches_oracle(gpu_lib, case):
+    H, W, om, sg, N, th = BANKS[case]
+    img = workloads.uniform_image(H, W, 520 + case)
+    thetas = workloads.orientations(N) if th is None else np.asarray(th)
+    g = loss_grad_gpu(gpu_lib, img, om, sg, N, th)
+    xs, ys = workloads.sample_pixels(H, W, 64, 530 + case)
+    ref = oracle.gabor_grad_points(img, om, sg, thetas, xs, ys)
+    err = np.abs(g[ys, xs] - ref).max() / np.abs(ref).max()
+    print(f"grad case {case}: max err / peak {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_autograd_gradient_matches_finite_differences(gpu_lib):
+    import torch
+    H, W = 96, 112
+    om, sg, N = [math.pi / 2, math.pi / 4], [2.0, 4.0], 8
+    img = workloads.uniform_image(H, W, 540)
+    g = loss_grad_gpu(gpu_lib, img, om, sg, N, None)
+    bank = gpu_lib.GaborBank(H, W, om, sg, N, None, 3.0, "zero", "fp32")
+    n = len(om) * N * H * W
+    R = int(math.floor(3 * max(sg) + 0.5))
+    h = 1e-3
+    xs, ys = workloads.sample_pixels(H, W, 24, 541)
+    fd = np.empty(len(xs))
+    for i, (x, y) in enumerate(zip(xs, ys)):
+        vals = []
+        for s in (+1, -1):
+            pert = img.copy()
+            pert[y, x] += s * h
+            F = bank(torch.from_numpy(pert).cuda()).cpu().numpy()
+            win = F[:, :, max(0, y - R):y + R + 1, max(0, x - R):x + R + 1].astype(np.complex128)
+            vals.append(np.sum(np.abs(win) ** 2) / n)
+        fd[i] = (vals[0] - vals[1]) / (2 * h)
+    bank.close()
+    err = np.abs(fd - g[ys, xs]).max() / np.abs(g[ys, xs]).max()
+    print(f"finite differences: max err / peak {err:.2e}")
+    assert err <= 5e-3
+
+
+def test_feature_layer_workload_sampled(gpu_lib):
+    """The differentiable-layer workload: a batch of 32 uniform 512^2 images,
+    8 orientations x 4 frequencies (sigma = pi / omega), zero boundary,
+    L = mean |F|^2 over the batch; gradients of the first and last image
+    checked against the oracle at sampled pixels."""
+    import torch
+    from paper_1704_05231_amd.autograd import GaborLayer
+    wl = workloads.bank_layer()
+    imgs = np.stack(wl.images)
+    B, H, W = imgs.shape
+    layer = GaborLayer(H, W, wl.omegas, wl.sigmas, wl.n_orient)
+    x = torch.from_numpy(imgs).cuda().requires_grad_(True)
+    F = layer(x)
+    loss = (F.real ** 2 + F.imag ** 2).mean()
+    loss.backward()
+    g = x.grad.cpu().numpy()
+    layer.close()
+    thetas = wl.thetas_or_default
+    for b in (0, B - 1):
+        xs, ys = workloads.sample_pixels(H, W, 8, 550 + b)
+        # the oracle's loss is the mean over one image's outputs: scale by 1/B
+        ref = oracle.gabor_grad_points(imgs[b], wl.omegas, wl.sigmas, thetas, xs, ys) / B
+        err = np.abs(g[b][ys, xs] - ref).max() / np.abs(ref).max()
+        print(f"layer image {b}: max err / peak {err:.2e}")
+        assert err <= 1e-5
