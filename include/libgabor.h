@@ -86,7 +86,10 @@ const char* gabor_status_string(gabor_status status);
  *                  unpaired orientations are computed on their own.
  *   radius_sigmas  truncation of S in units of sigma (3.0 gives R = 3 sigma).
  *   boundary       rule for samples outside the image.
- *   precision      arithmetic of the Gaussian contractions.
+ *   precision      arithmetic of the Gaussian contractions.  Frequencies the
+ *                  fused kernel cannot take (R > 56, or planes of 2^29 pixels
+ *                  and more) run the FP32 two-pass kernels whatever the
+ *                  precision.
  *   hip_stream     stream used to upload the plan's tables.
  *
  * The plan owns device memory for its tap tables and any intermediate
@@ -134,6 +137,37 @@ gabor_status gabor_bank_apply(gabor_plan plan, const float* d_image,
  */
 gabor_status gabor_bank_apply_adjoint(gabor_plan plan, const void* d_grad_out, float* d_grad_image,
                                       int64_t grad_row_stride_elems, void* hip_stream);
+
+/*
+ * Batched bank: many images of uneven sizes through one plan.
+ *
+ * gabor_batch_create binds n_images device images (d_images[i], heights[i]
+ * x widths[i], row stride row_strides[i] >= widths[i]; every image no larger
+ * than the plan's height x width) to device outputs d_outs[i], complex64
+ * [O][N][heights[i]][widths[i]].  The host arrays are read during the call
+ * only; the batch keeps the pointers and owns a device tile table (one tile
+ * per image, horizontal result and strip segment).  The plan must outlive
+ * the batch; a batch shares its plan's streams and workspace, so the two are
+ * not used concurrently.
+ *
+ * gabor_batch_apply runs Algorithm 1 on every bound image: one persistent
+ * launch per operand size of the fused kernel, each over the tiles of all
+ * images, plus image-by-image FP32 two-pass launches for frequencies outside
+ * the fused kernel's range (R > 56, or planes of 2^29 pixels and more).  It
+ * allocates and copies nothing, so it may be captured in a HIP graph and
+ * replayed; the images are read and the outputs written at each replay.
+ */
+typedef struct gabor_batch_s* gabor_batch;
+
+gabor_status gabor_batch_create(gabor_batch* out, gabor_plan plan, int32_t n_images,
+                                const float* const* d_images, const int32_t* heights,
+                                const int32_t* widths, const int64_t* row_strides,
+                                void* const* d_outs, void* hip_stream);
+gabor_status gabor_batch_apply(gabor_batch batch, void* hip_stream);
+/* Number of persistent launches and of tiles of a batch (either may be NULL). */
+gabor_status gabor_batch_info(gabor_batch batch, int32_t* n_launches, int64_t* n_tiles);
+/* Release a batch's tile table.  NULL is accepted (no-op). */
+gabor_status gabor_batch_destroy(gabor_batch batch);
 
 /* Release a plan and its device memory.  NULL is accepted (no-op). */
 gabor_status gabor_bank_destroy(gabor_plan plan);

@@ -29,7 +29,8 @@ PRECISION = {"fp32": 0, "bf16_split": 1, "fp16_split": 2, "bf16": 3, "fp16": 4}
 
 # Every symbol include/libgabor.h declares; the CPU tests check the exports.
 EXPORTS = ["gabor_status_string", "gabor_bank_plan", "gabor_bank_apply", "gabor_bank_apply_adjoint",
-           "gabor_bank_destroy", "lsdft_apply", "lsdft_work", "gabor_bank_plan_info", "gabor_profile_enable",
+           "gabor_bank_destroy", "gabor_batch_create", "gabor_batch_apply", "gabor_batch_info",
+           "gabor_batch_destroy", "lsdft_apply", "lsdft_work", "gabor_bank_plan_info", "gabor_profile_enable",
            "gabor_profile_read"]
 
 
@@ -81,6 +82,14 @@ def load():
     lib.gabor_bank_destroy.restype = ctypes.c_int
     lib.gabor_bank_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
     lib.gabor_bank_plan_info.restype = ctypes.c_int
+    lib.gabor_batch_create.argtypes = [ctypes.POINTER(P), P, i32, P, P, P, P, P, P]
+    lib.gabor_batch_create.restype = ctypes.c_int
+    lib.gabor_batch_apply.argtypes = [P, P]
+    lib.gabor_batch_apply.restype = ctypes.c_int
+    lib.gabor_batch_info.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    lib.gabor_batch_info.restype = ctypes.c_int
+    lib.gabor_batch_destroy.argtypes = [P]
+    lib.gabor_batch_destroy.restype = ctypes.c_int
     lib.lsdft_apply.argtypes = [P, i32, i32, i64, i32, i32, f64, ctypes.c_int, ctypes.c_int, P, P]
     lib.lsdft_apply.restype = ctypes.c_int
     lib.lsdft_work.argtypes = [i32, i32, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -151,6 +160,36 @@ def gabor_bank_apply_adjoint(plan, d_grad_out: int, d_grad_image: int, grad_row_
 
 def gabor_bank_destroy(plan):
     _check(load().gabor_bank_destroy(plan), "gabor_bank_destroy")
+
+
+def gabor_batch_create(plan, d_images, heights, widths, row_strides, d_outs, stream=None):
+    n = len(d_images)
+    if not (len(heights) == len(widths) == len(row_strides) == len(d_outs) == n):
+        raise ValueError("batch arrays must have one entry per image")
+    imgs = (ctypes.c_void_p * n)(*[int(x) for x in d_images])
+    outs = (ctypes.c_void_p * n)(*[int(x) for x in d_outs])
+    hs = np.ascontiguousarray(heights, dtype=np.int32)
+    ws = np.ascontiguousarray(widths, dtype=np.int32)
+    ss = np.ascontiguousarray(row_strides, dtype=np.int64)
+    batch = ctypes.c_void_p()
+    st = load().gabor_batch_create(ctypes.byref(batch), plan, n, ctypes.cast(imgs, ctypes.c_void_p), _p(hs),
+                                   _p(ws), _p(ss), ctypes.cast(outs, ctypes.c_void_p), _stream(stream))
+    _check(st, "gabor_batch_create")
+    return batch
+
+
+def gabor_batch_apply(batch, stream=None):
+    _check(load().gabor_batch_apply(batch, _stream(stream)), "gabor_batch_apply")
+
+
+def gabor_batch_info(batch) -> tuple[int, int]:
+    nl, nt = ctypes.c_int32(), ctypes.c_int64()
+    _check(load().gabor_batch_info(batch, ctypes.byref(nl), ctypes.byref(nt)), "gabor_batch_info")
+    return nl.value, nt.value
+
+
+def gabor_batch_destroy(batch):
+    _check(load().gabor_batch_destroy(batch), "gabor_batch_destroy")
 
 
 def lsdft_apply(d_image: int, height, width, row_stride_elems, m_y, m_x, sigma, boundary="zero",
@@ -270,6 +309,49 @@ class GaborBank:
         if self._plan:
             gabor_bank_destroy(self._plan)
             self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class GaborBatch:
+    """Images of uneven sizes bound to one bank: ``batch()`` fills the bound
+    complex64 outputs [O, N, h_i, w_i] (``batch.outputs``).  The images and
+    outputs must stay alive and in place while the batch exists."""
+
+    def __init__(self, bank: "GaborBank", images, outputs=None, stream=None):
+        import torch
+        for im in images:
+            if im.dtype != torch.float32 or im.dim() != 2 or not im.is_cuda or im.stride(1) != 1:
+                raise ValueError("images must be row-major 2-D float32 GPU tensors")
+        if outputs is None:
+            outputs = [torch.empty((bank.n_freq, bank.n_orient, im.shape[0], im.shape[1]),
+                                   dtype=torch.complex64, device=im.device) for im in images]
+        for im, o in zip(images, outputs):
+            if (o.dtype != torch.complex64 or not o.is_contiguous()
+                    or tuple(o.shape) != (bank.n_freq, bank.n_orient, im.shape[0], im.shape[1])):
+                raise ValueError("outputs must be contiguous complex64 [O, N, h, w] tensors")
+        self.bank, self.images, self.outputs = bank, list(images), list(outputs)
+        self._batch = gabor_batch_create(bank._plan, [im.data_ptr() for im in images],
+                                         [im.shape[0] for im in images], [im.shape[1] for im in images],
+                                         [im.stride(0) for im in images], [o.data_ptr() for o in outputs],
+                                         stream)
+
+    def __call__(self, stream=None):
+        gabor_batch_apply(self._batch, stream)
+        return self.outputs
+
+    @property
+    def info(self) -> tuple[int, int]:
+        return gabor_batch_info(self._batch)
+
+    def close(self):
+        if self._batch:
+            gabor_batch_destroy(self._batch)
+            self._batch = None
 
     def __del__(self):
         try:

@@ -1,0 +1,228 @@
+// Batched bank: many images of uneven sizes through one plan (Algorithm 1 per
+// image).  gabor_batch_create binds the images and outputs once and uploads
+// a tile table; gabor_batch_apply then only launches, so it allocates and
+// copies nothing and may be captured in a HIP graph and replayed.
+//
+// Frequencies on the fused kernel are grouped by operand quarter Q; each
+// group is one persistent launch over the tiles (image, job, strip segment)
+// of every image, ordered by decreasing length so that the last round of
+// workgroups is short.  Frequencies outside the fused kernel's range run the
+// FP32 two-pass kernels image by image on the caller's stream.
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "gabor_plan_impl.h"
+
+namespace {
+
+struct BatchGroup {
+    int q;
+    int first_tile, n_tiles;
+    int64_t weight;            // total tile steps, for ordering the launches
+};
+
+}  // namespace
+
+struct gabor_batch_s {
+    gabor_plan plan = nullptr;
+    int32_t n = 0;
+    std::vector<BatchImage> images;          // host copy (pointers, sizes)
+    std::vector<BatchGroup> groups;          // fused launches, heaviest first
+    std::vector<int> twopass_freqs;          // frequencies on the two-pass kernels
+    BatchImage* d_images = nullptr;
+    BatchFreq* d_freqs = nullptr;
+    BatchTile* d_tiles = nullptr;
+    int64_t tiles = 0;
+};
+
+namespace {
+
+void batch_release(gabor_batch b)
+{
+    if (!b) return;
+    if (b->d_images) (void)hipFree(b->d_images);
+    if (b->d_freqs) (void)hipFree(b->d_freqs);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" gabor_status gabor_batch_create(gabor_batch* out, gabor_plan p, int32_t n_images,
+                                           const float* const* d_images, const int32_t* heights,
+                                           const int32_t* widths, const int64_t* row_strides,
+                                           void* const* d_outs, void* hip_stream)
+{
+    if (!out) return GABOR_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!p || n_images <= 0 || !d_images || !heights || !widths || !row_strides || !d_outs)
+        return GABOR_ERR_INVALID_ARG;
+    for (int i = 0; i < n_images; ++i) {
+        if (!d_images[i] || !d_outs[i]) return GABOR_ERR_INVALID_ARG;
+        if (heights[i] <= 0 || widths[i] <= 0 || heights[i] > p->H || widths[i] > p->W) return GABOR_ERR_INVALID_ARG;
+        if (row_strides[i] < widths[i]) return GABOR_ERR_INVALID_ARG;
+        if (!p->fjobs.empty() && (int64_t)(heights[i] - 1) * row_strides[i] + widths[i] >= (int64_t(1) << 30))
+            return GABOR_ERR_UNSUPPORTED;
+    }
+    gabor_batch b = new (std::nothrow) gabor_batch_s;
+    if (!b) return GABOR_ERR_OUT_OF_MEMORY;
+    b->plan = p;
+    b->n = n_images;
+    const int sx = stream_strip_width();
+    for (int i = 0; i < n_images; ++i) {
+        BatchImage im{};
+        im.img = d_images[i];
+        im.out = (float2*)d_outs[i];
+        im.stride = row_strides[i];
+        im.H = heights[i];
+        im.W = widths[i];
+        im.n_xs = (widths[i] + sx - 1) / sx;
+        b->images.push_back(im);
+    }
+    std::vector<BatchFreq> freqs(p->O);
+    for (int f = 0; f < p->O; ++f) {
+        const FreqLaunch& fl = p->launches[f];
+        BatchFreq& bf = freqs[f];
+        bf.R = p->freqs[f].R;
+        bf.seg_rows = fl.seg_rows;
+        bf.in_scale = fl.in_scale;
+        bf.mid_scale = fl.mid_scale;
+        bf.out_scale = fl.out_scale;
+        bf.tap_scale[0] = fl.tap_scale[0];
+        bf.tap_scale[1] = fl.tap_scale[1];
+        if (!fl.fused) b->twopass_freqs.push_back(f);
+    }
+    // Tiles per quarter: image-major, then segment, strip and job (jobs of a
+    // strip share its image rows), then stably sorted by decreasing length.
+    std::vector<int> qs;
+    for (int f = 0; f < p->O; ++f)
+        if (p->launches[f].fused && std::find(qs.begin(), qs.end(), p->launches[f].q) == qs.end())
+            qs.push_back(p->launches[f].q);
+    std::vector<BatchTile> tiles;
+    for (int q : qs) {
+        BatchGroup g{};
+        g.q = q;
+        g.first_tile = (int)tiles.size();
+        std::vector<std::pair<int, BatchTile>> tl;        // (steps, tile)
+        for (int i = 0; i < n_images; ++i)
+            for (int f = 0; f < p->O; ++f) {
+                const FreqLaunch& fl = p->launches[f];
+                if (!fl.fused || fl.q != q) continue;
+                const int h = heights[i], seg = fl.seg_rows;
+                const int n_ys = (h + seg - 1) / seg;
+                const int lead = 4 * q / 16;
+                for (int ys = 0; ys < n_ys; ++ys) {
+                    const int steps = (std::min(seg, h - ys * seg) + 15) / 16 + lead;
+                    for (int xs = 0; xs < b->images[i].n_xs; ++xs)
+                        for (int j = 0; j < fl.count; ++j) {
+                            BatchTile t{};
+                            t.image = i;
+                            t.job = fl.first + j;
+                            t.freq = f;
+                            t.rest = xs + ys * b->images[i].n_xs;
+                            tl.push_back({steps, t});
+                            g.weight += steps;
+                        }
+                }
+            }
+        std::stable_sort(tl.begin(), tl.end(), [](const auto& a, const auto& c) { return a.first > c.first; });
+        if ((int64_t)tiles.size() + (int64_t)tl.size() > 0x7fffffffLL) {
+            batch_release(b);
+            return GABOR_ERR_UNSUPPORTED;
+        }
+        for (auto& e : tl) tiles.push_back(e.second);
+        g.n_tiles = (int)tl.size();
+        b->groups.push_back(g);
+    }
+    std::stable_sort(b->groups.begin(), b->groups.end(),
+                     [](const BatchGroup& a, const BatchGroup& c) { return a.weight * a.q > c.weight * c.q; });
+    b->tiles = (int64_t)tiles.size();
+
+    hipStream_t stream = (hipStream_t)hip_stream;
+    const size_t ib = b->images.size() * sizeof(BatchImage), fb = freqs.size() * sizeof(BatchFreq);
+    const size_t tb = std::max<size_t>(1, tiles.size()) * sizeof(BatchTile);
+    hipError_t e = hipMalloc((void**)&b->d_images, ib);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_freqs, fb);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_tiles, tb);
+    if (e != hipSuccess) {
+        batch_release(b);
+        return e == hipErrorOutOfMemory ? GABOR_ERR_OUT_OF_MEMORY : GABOR_ERR_DEVICE;
+    }
+    if (hipMemcpyAsync(b->d_images, b->images.data(), ib, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(b->d_freqs, freqs.data(), fb, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        (!tiles.empty() &&
+         hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice, stream) != hipSuccess) ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+        batch_release(b);
+        return GABOR_ERR_DEVICE;
+    }
+    *out = b;
+    return GABOR_OK;
+}
+
+extern "C" gabor_status gabor_batch_apply(gabor_batch b, void* hip_stream)
+{
+    if (!b || !b->plan) return GABOR_ERR_INVALID_ARG;
+    gabor_plan p = b->plan;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    // Fork: launch j > 0 goes to auxiliary stream (j - 1) mod n after the
+    // work already queued on the caller's stream.
+    const int n_aux = (int)p->aux.size();
+    if (n_aux > 0 && b->groups.size() > 1) {
+        if (hipEventRecord(p->fork_ev[0], stream) != hipSuccess) return GABOR_ERR_DEVICE;
+        for (int k = 0; k < n_aux; ++k)
+            if (hipStreamWaitEvent(p->aux[k], p->fork_ev[0], 0) != hipSuccess) return GABOR_ERR_DEVICE;
+    }
+    const bool fork = n_aux > 0 && b->groups.size() > 1;
+    for (size_t j = 0; j < b->groups.size(); ++j) {
+        const BatchGroup& g = b->groups[j];
+        hipStream_t ls = (j == 0 || !fork) ? stream : p->aux[(j - 1) % n_aux];
+        BatchArgs a{};
+        a.images = b->d_images;
+        a.freqs = b->d_freqs;
+        a.tiles = b->d_tiles + g.first_tile;
+        a.jobs = p->d_fjobs;
+        a.taps = p->d_taps;
+        a.n_tiles = g.n_tiles;
+        a.boundary = p->boundary;
+        if (launch_batch(p->fused_op, a, g.q, ls) != hipSuccess) return GABOR_ERR_DEVICE;
+    }
+    // Two-pass frequencies, image by image (they share the plan's J planes).
+    for (const BatchImage& im : b->images) {
+        for (size_t gi = 0; gi < p->row_groups.size(); ++gi) {
+            const RowGroup& rg = p->row_groups[gi];
+            if (launch_row_fp32(im.img, im.stride, im.H, im.W, p->boundary, p->freqs[rg.freq], rg, p->d_taps,
+                                p->d_J, stream) != hipSuccess)
+                return GABOR_ERR_DEVICE;
+        }
+        for (int f : b->twopass_freqs) {
+            const FreqLaunch& fl = p->launches[f];
+            if (launch_col_fp32(p->d_J, im.H, im.W, p->boundary, p->freqs[f], p->d_jobs + fl.first, fl.count,
+                                p->d_taps, im.out, stream) != hipSuccess)
+                return GABOR_ERR_DEVICE;
+        }
+    }
+    if (fork) {
+        for (int k = 0; k < n_aux; ++k)
+            if (hipEventRecord(p->join_ev[k], p->aux[k]) != hipSuccess ||
+                hipStreamWaitEvent(stream, p->join_ev[k], 0) != hipSuccess)
+                return GABOR_ERR_DEVICE;
+    }
+    return GABOR_OK;
+}
+
+extern "C" gabor_status gabor_batch_info(gabor_batch b, int32_t* n_launches, int64_t* n_tiles)
+{
+    if (!b) return GABOR_ERR_INVALID_ARG;
+    if (n_launches) *n_launches = (int32_t)b->groups.size();
+    if (n_tiles) *n_tiles = b->tiles;
+    return GABOR_OK;
+}
+
+extern "C" gabor_status gabor_batch_destroy(gabor_batch b)
+{
+    batch_release(b);
+    return GABOR_OK;
+}

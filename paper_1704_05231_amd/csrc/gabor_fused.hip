@@ -562,6 +562,80 @@ __global__ __launch_bounds__(kThreads) void k_lsdft(StreamArgs a, LsdftTaps t)
     else stream_body<OP, Q, false, false, true>(a, jb, rest, &t, u, v);
 }
 
+// Persistent batch kernel: workgroup g takes tiles g, g + G, g + 2G, ...
+// (after the XCD remap, so neighbouring tiles, which share image strips,
+// stay on one XCD's L2).  The host orders tiles by decreasing length.
+template <int OP, int Q>
+__global__ __launch_bounds__(kThreads) void k_stream_batch(BatchArgs b)
+{
+    const int lid = xcd_local_id(blockIdx.x, gridDim.x);
+    for (int t = lid; t < b.n_tiles; t += gridDim.x) {
+        const BatchTile tl = b.tiles[t];
+        const BatchImage im = b.images[tl.image];
+        const BatchFreq fq = b.freqs[tl.freq];
+        StreamArgs a{};
+        a.img = im.img;
+        a.stride = im.stride;
+        a.H = im.H;
+        a.W = im.W;
+        a.boundary = b.boundary;
+        a.R = fq.R;
+        a.seg_rows = fq.seg_rows;
+        a.n_xs = im.n_xs;
+        a.jobs = b.jobs;
+        a.taps = b.taps;
+        a.out = im.out;
+        a.in_scale = fq.in_scale;
+        a.mid_scale = fq.mid_scale;
+        a.out_scale = fq.out_scale;
+        a.tap_scale[0] = fq.tap_scale[0];
+        a.tap_scale[1] = fq.tap_scale[1];
+        const FusedJob jb = b.jobs[tl.job];
+        lds_barrier();                                   // the previous tile is done with LDS
+        if (jb.j_real) stream_body<OP, Q, true, false, false>(a, jb, tl.rest, nullptr, 0, 0);
+        else if (jb.c_real) stream_body<OP, Q, false, true, false>(a, jb, tl.rest, nullptr, 0, 0);
+        else stream_body<OP, Q, false, false, false>(a, jb, tl.rest, nullptr, 0, 0);
+    }
+}
+
+template <int OP, int Q>
+hipError_t launch_bq(const BatchArgs& b, hipStream_t stream)
+{
+    const size_t lds = stream_lds_bytes(OP, Q);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_stream_batch<OP, Q>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    // Resident capacity, found once per instantiation and device.
+    static int per_cu[64] = {0}, n_cu[64] = {0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (per_cu[dev] == 0) {
+        int blocks = 0, cus = 0;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_stream_batch<OP, Q>, kThreads, lds)) != hipSuccess)
+            return e;
+        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+        n_cu[dev] = cus > 0 ? cus : 1;
+        per_cu[dev] = blocks > 0 ? blocks : 1;
+    }
+    const long long cap = (long long)per_cu[dev] * n_cu[dev];
+    const int grid = (int)(b.n_tiles < cap ? b.n_tiles : cap);
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_stream_batch<OP, Q>), dim3(grid), dim3(kThreads), lds, stream, b);
+    return hipGetLastError();
+}
+
+template <int OP, int... Qs>
+hipError_t launch_batch_q(const BatchArgs& b, int Q, hipStream_t stream)
+{
+    hipError_t e = hipErrorInvalidValue;
+    ((Q == Qs ? (void)(e = launch_bq<OP, Qs>(b, stream)) : (void)0), ...);
+    return e;
+}
+
 template <int OP, int Q>
 hipError_t launch_q(const StreamArgs& a, int n_blocks, hipStream_t stream)
 {
@@ -634,7 +708,30 @@ hipError_t lsdft_form<GABOR_FORM>(const StreamArgs& a, const LsdftTaps& t, int Q
         return launch_lsdft_q<GABOR_FORM, 8, 16, 24>(a, t, Q, n_blocks, stream);
 }
 
+template <>
+hipError_t batch_form<GABOR_FORM>(const BatchArgs& b, int Q, hipStream_t stream)
+{
+    if constexpr (GABOR_FORM == FUSED_F32)
+        return launch_batch_q<GABOR_FORM, 4, 8, 12, 16, 20, 24, 28, 32>(b, Q, stream);
+    else
+        return launch_batch_q<GABOR_FORM, 8, 16, 24, 32>(b, Q, stream);
+}
+
 #if GABOR_FORM == 0
+hipError_t launch_batch(int op, const BatchArgs& b, int Q, hipStream_t stream)
+{
+    if (b.n_tiles <= 0) return hipSuccess;
+    if (Q > kStreamMaxQuarter || !b.images || !b.freqs || !b.tiles || !b.jobs || !b.taps) return hipErrorInvalidValue;
+    switch (op) {
+        case FUSED_F32: return batch_form<FUSED_F32>(b, Q, stream);
+        case FUSED_BF16: return batch_form<FUSED_BF16>(b, Q, stream);
+        case FUSED_BF16X3: return batch_form<FUSED_BF16X3>(b, Q, stream);
+        case FUSED_F16: return batch_form<FUSED_F16>(b, Q, stream);
+        case FUSED_F16X3: return batch_form<FUSED_F16X3>(b, Q, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
 int stream_quarter(int op, int R)
 {
     const int need = 16 + 2 * R;                         // inputs per 16-block

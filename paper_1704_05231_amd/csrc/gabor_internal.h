@@ -72,6 +72,35 @@ struct StreamArgs {
     float tap_scale[2];        // horizontal, vertical tap scales
 };
 
+// Batched bank (one persistent launch per operand quarter): images of any
+// size up to the plan's, each tile one (image, job, strip segment).
+struct BatchImage {
+    const float* img;
+    float2* out;               // [O][N][H][W] of this image
+    int64_t stride;
+    int32_t H, W, n_xs, pad_;
+};
+struct BatchFreq {
+    int32_t R, seg_rows;
+    float in_scale, mid_scale, out_scale, tap_scale[2];
+    int32_t pad_;
+};
+struct BatchTile {
+    int32_t image, job, freq;  // job indexes the plan's fused job table
+    int32_t rest;              // strip + segment * n_xs of the image
+};
+struct BatchArgs {
+    const BatchImage* images;
+    const BatchFreq* freqs;
+    const BatchTile* tiles;
+    const FusedJob* jobs;
+    const float* taps;
+    int32_t n_tiles, boundary;
+};
+// Launches the persistent batch kernel of one form and quarter with as many
+// workgroups as fit on the device at once (at most n_tiles).
+hipError_t launch_batch(int op, const BatchArgs& b, int Q, hipStream_t stream);
+
 // Localized SDFT taps, passed by value as a kernel argument (no device
 // tables): axis 0 is x (the horizontal pass), axis 1 is y.
 constexpr int kLsdftMaxM = 64;
@@ -92,9 +121,11 @@ hipError_t launch_lsdft(int op, const StreamArgs& a, const LsdftTaps& t, int Q, 
 template <int OP> hipError_t stream_form(const StreamArgs& a, int Q, int n_blocks, hipStream_t stream);
 template <int OP> hipError_t lsdft_form(const StreamArgs& a, const LsdftTaps& t, int Q, int n_blocks,
                                         hipStream_t stream);
+template <int OP> hipError_t batch_form(const BatchArgs& b, int Q, hipStream_t stream);
 #define GABOR_DECLARE_FORM(OP)                                                                   \
     template <> hipError_t stream_form<OP>(const StreamArgs&, int, int, hipStream_t);            \
-    template <> hipError_t lsdft_form<OP>(const StreamArgs&, const LsdftTaps&, int, int, hipStream_t);
+    template <> hipError_t lsdft_form<OP>(const StreamArgs&, const LsdftTaps&, int, int, hipStream_t); \
+    template <> hipError_t batch_form<OP>(const BatchArgs&, int, hipStream_t);
 GABOR_DECLARE_FORM(FUSED_F32)
 GABOR_DECLARE_FORM(FUSED_BF16)
 GABOR_DECLARE_FORM(FUSED_BF16X3)

@@ -22,60 +22,7 @@
 
 using namespace gabor;
 
-namespace {
-// How one frequency is computed: the fused kernel (jobs in fjobs) or the
-// two-pass kernels (jobs in jobs, J planes written by the row groups).
-struct FreqLaunch {
-    bool fused;
-    int q;            // operand quarter: contracted length 4q (fused)
-    int seg_rows;     // strip segment rows (fused)
-    float in_scale, mid_scale, out_scale, tap_scale[2];
-    int first;        // first job
-    int count;        // jobs
-    int64_t macs;     // algorithmic real MACs of the launch (vertical, plus horizontal when fused)
-    int64_t bytes;    // algorithmic bytes of the launch
-};
-const char* const kFusedNames[5] = {"stream_f32", "stream_bf16", "stream_bf16x3", "stream_f16", "stream_f16x3"};
-enum { ALGO_AUTO = 0, ALGO_TWOPASS = 1 };
-}  // namespace
-
-struct gabor_plan_s {
-    int32_t H = 0, W = 0, O = 0, N = 0;
-    int32_t boundary = 0;
-    int32_t precision = 0;
-    std::vector<FreqDesc> freqs;
-    std::vector<RowGroup> row_groups;
-    std::vector<int64_t> row_group_macs;       // per row group
-    std::vector<ColJob> jobs;              // two-pass vertical jobs
-    std::vector<FusedJob> fjobs;           // fused jobs
-    std::vector<FreqLaunch> launches;      // per frequency
-    std::vector<int> order;                // launch order of the frequencies
-    std::vector<AdjJob> ajobs;             // adjoint jobs (every horizontal result)
-    int adj_max_kp = 0;
-    int64_t adj_row_macs = 0, adj_col_macs = 0;
-    AdjJob* d_ajobs = nullptr;
-    float2* d_adjJ = nullptr;              // adjoint workspace, allocated by the first adjoint call
-    int fused_op = FUSED_F32;
-    int32_t n_planes = 0;
-    int32_t n_row_passes = 0, n_col_passes = 0;
-    int64_t row_macs = 0, col_macs = 0;
-    int64_t workspace_bytes = 0;
-    float* d_taps = nullptr;
-    ColJob* d_jobs = nullptr;
-    FusedJob* d_fjobs = nullptr;
-    float2* d_J = nullptr;
-    // Fork/join of the per-frequency launches: auxiliary streams (default
-    // priority) joined back to the caller's stream with events.
-    std::vector<hipStream_t> aux;
-    std::vector<hipEvent_t> fork_ev, join_ev;
-    // per-kernel timing
-    bool prof = false;
-    struct Pending { int kind; hipEvent_t a, b; };
-    std::vector<Pending> pending;
-    std::vector<hipEvent_t> event_pool;
-    std::vector<std::string> kind_names;
-    std::vector<gabor_kernel_stat> stats;
-};
+#include "gabor_plan_impl.h"
 
 namespace {
 
@@ -335,10 +282,8 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
         }
         const int q = stream_quarter(p->fused_op, fd.R);
         const bool fused = q <= kStreamMaxQuarter && algo != ALGO_TWOPASS && npix < (int64_t(1) << 29);
-        if (!fused && precision != GABOR_PREC_FP32) {
-            release(p);
-            return GABOR_ERR_UNSUPPORTED;
-        }
+        // Frequencies outside the fused kernel's range run the FP32 two-pass
+        // kernels whatever the requested precision (never less accurate).
         FreqLaunch fl{};
         fl.fused = fused;
         fl.q = q;

@@ -132,3 +132,15 @@ def test_lsdft_work_counts():
 def test_adjoint_rejects_null_arguments():
     lib = binding.load()
     assert lib.gabor_bank_apply_adjoint(None, ctypes.c_void_p(16), ctypes.c_void_p(16), 8, None) == 1
+
+
+def test_batch_rejects_null_arguments():
+    lib = binding.load()
+    P = ctypes.c_void_p
+    batch = ctypes.c_void_p(99)
+    assert lib.gabor_batch_create(None, None, 1, None, None, None, None, None, None) == 1
+    assert lib.gabor_batch_create(ctypes.byref(batch), None, 1, None, None, None, None, None, None) == 1
+    assert batch.value is None
+    assert lib.gabor_batch_apply(None, None) == 1
+    assert lib.gabor_batch_info(None, None, None) == 1
+    assert lib.gabor_batch_destroy(None) == 0
