@@ -217,6 +217,23 @@ gabor_status lsdft_apply(const float* d_image, int32_t height, int32_t width,
 gabor_status lsdft_work(int32_t height, int32_t width, int32_t m_y, int32_t m_x,
                         int64_t* real_macs, int64_t* bytes);
 
+/*
+ * Autotuning (schedule only; results do not depend on it).  Each frequency
+ * on the fused kernel streams strip segments of seg_rows image rows per
+ * workgroup (a multiple of 16; each segment recomputes a lead-in of about 2R
+ * rows of the horizontal pass).  gabor_bank_autotune times every candidate
+ * segment height per fused frequency on the caller's image and output
+ * buffers (d_out is overwritten), keeps the fastest median of `reps` timed
+ * launches, and synchronises hip_stream.  get/set copy the chosen heights
+ * (n = number of frequencies; 0 for frequencies on the two-pass kernels) so
+ * that a caller can cache them; set rejects heights that are not positive
+ * multiples of 16.  Batches created afterwards use the new heights.
+ */
+gabor_status gabor_bank_autotune(gabor_plan plan, const float* d_image, int64_t row_stride_elems,
+                                 void* d_out, int32_t reps, void* hip_stream);
+gabor_status gabor_bank_get_tuning(gabor_plan plan, int32_t* seg_rows, int32_t capacity, int32_t* n);
+gabor_status gabor_bank_set_tuning(gabor_plan plan, const int32_t* seg_rows, int32_t n);
+
 typedef struct gabor_plan_info {
     int32_t height, width, n_freq, n_orient;
     int32_t max_radius;          /* largest R over the frequencies */

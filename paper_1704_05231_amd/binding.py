@@ -30,7 +30,8 @@ PRECISION = {"fp32": 0, "bf16_split": 1, "fp16_split": 2, "bf16": 3, "fp16": 4}
 # Every symbol include/libgabor.h declares; the CPU tests check the exports.
 EXPORTS = ["gabor_status_string", "gabor_bank_plan", "gabor_bank_apply", "gabor_bank_apply_adjoint",
            "gabor_bank_destroy", "gabor_batch_create", "gabor_batch_apply", "gabor_batch_info",
-           "gabor_batch_destroy", "lsdft_apply", "lsdft_work", "gabor_bank_plan_info", "gabor_profile_enable",
+           "gabor_batch_destroy", "gabor_bank_autotune", "gabor_bank_get_tuning", "gabor_bank_set_tuning",
+           "lsdft_apply", "lsdft_work", "gabor_bank_plan_info", "gabor_profile_enable",
            "gabor_profile_read"]
 
 
@@ -90,6 +91,12 @@ def load():
     lib.gabor_batch_info.restype = ctypes.c_int
     lib.gabor_batch_destroy.argtypes = [P]
     lib.gabor_batch_destroy.restype = ctypes.c_int
+    lib.gabor_bank_autotune.argtypes = [P, P, i64, P, i32, P]
+    lib.gabor_bank_autotune.restype = ctypes.c_int
+    lib.gabor_bank_get_tuning.argtypes = [P, P, i32, ctypes.POINTER(i32)]
+    lib.gabor_bank_get_tuning.restype = ctypes.c_int
+    lib.gabor_bank_set_tuning.argtypes = [P, P, i32]
+    lib.gabor_bank_set_tuning.restype = ctypes.c_int
     lib.lsdft_apply.argtypes = [P, i32, i32, i64, i32, i32, f64, ctypes.c_int, ctypes.c_int, P, P]
     lib.lsdft_apply.restype = ctypes.c_int
     lib.lsdft_work.argtypes = [i32, i32, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -160,6 +167,24 @@ def gabor_bank_apply_adjoint(plan, d_grad_out: int, d_grad_image: int, grad_row_
 
 def gabor_bank_destroy(plan):
     _check(load().gabor_bank_destroy(plan), "gabor_bank_destroy")
+
+
+def gabor_bank_autotune(plan, d_image: int, row_stride_elems: int, d_out: int, reps: int = 5, stream=None):
+    _check(load().gabor_bank_autotune(plan, ctypes.c_void_p(d_image), int(row_stride_elems),
+                                      ctypes.c_void_p(d_out), int(reps), _stream(stream)), "gabor_bank_autotune")
+
+
+def gabor_bank_get_tuning(plan) -> list[int]:
+    n = ctypes.c_int32()
+    _check(load().gabor_bank_get_tuning(plan, None, 0, ctypes.byref(n)), "gabor_bank_get_tuning")
+    arr = np.zeros(n.value, dtype=np.int32)
+    _check(load().gabor_bank_get_tuning(plan, _p(arr), arr.size, ctypes.byref(n)), "gabor_bank_get_tuning")
+    return [int(v) for v in arr]
+
+
+def gabor_bank_set_tuning(plan, seg_rows):
+    arr = np.ascontiguousarray(seg_rows, dtype=np.int32)
+    _check(load().gabor_bank_set_tuning(plan, _p(arr), arr.size), "gabor_bank_set_tuning")
 
 
 def gabor_batch_create(plan, d_images, heights, widths, row_strides, d_outs, stream=None):
@@ -262,6 +287,11 @@ class GaborBank:
         self.n_freq = _f64(omegas).size
         self.n_orient = int(n_orient)
         self.precision = precision
+        self.params = {"height": self.height, "width": self.width,
+                       "omegas": [float(v) for v in _f64(omegas)], "sigmas": [float(v) for v in _f64(sigmas)],
+                       "n_orient": self.n_orient,
+                       "thetas": None if thetas is None else [float(v) for v in thetas],
+                       "radius_sigmas": float(radius_sigmas), "boundary": boundary, "precision": precision}
         self._plan = gabor_bank_plan(height, width, omegas, sigmas, self.n_orient, thetas,
                                      radius_sigmas, boundary, precision)
 
@@ -298,6 +328,23 @@ class GaborBank:
         gabor_bank_apply_adjoint(self._plan, grad_out.data_ptr(), grad_img.data_ptr(), grad_img.stride(0),
                                  stream)
         return grad_img
+
+    def autotune(self, img, out=None, reps: int = 5, stream=None) -> list[int]:
+        """Time the candidate schedules on img (and out, overwritten); keep the fastest."""
+        import torch
+        if out is None:
+            out = torch.empty((self.n_freq, self.n_orient, self.height, self.width),
+                              dtype=torch.complex64, device=img.device)
+        gabor_bank_autotune(self._plan, img.data_ptr(), img.stride(0), out.data_ptr(), reps, stream)
+        return self.tuning
+
+    @property
+    def tuning(self) -> list[int]:
+        return gabor_bank_get_tuning(self._plan)
+
+    @tuning.setter
+    def tuning(self, seg_rows):
+        gabor_bank_set_tuning(self._plan, seg_rows)
 
     def profile(self, enable: bool = True):
         gabor_profile_enable(self._plan, enable)

@@ -128,6 +128,35 @@ struct RowPass {
     int32_t job;    // index of the vertical job consuming it
 };
 
+
+// One fused-kernel launch: all jobs of frequency i over the whole image,
+// strip segments of seg_rows rows.
+hipError_t launch_fused_freq(gabor_plan p, int i, const float* d_image, int64_t stride, void* d_out,
+                             int seg_rows, hipStream_t s)
+{
+    const FreqLaunch& fl = p->launches[i];
+    StreamArgs sa{};
+    sa.img = d_image;
+    sa.stride = stride;
+    sa.H = p->H;
+    sa.W = p->W;
+    sa.boundary = p->boundary;
+    sa.R = p->freqs[i].R;
+    sa.seg_rows = seg_rows;
+    sa.n_xs = (p->W + stream_strip_width() - 1) / stream_strip_width();
+    sa.n_ys = (p->H + seg_rows - 1) / seg_rows;
+    sa.n_jobs = fl.count;
+    sa.jobs = p->d_fjobs + fl.first;
+    sa.taps = p->d_taps;
+    sa.out = (float2*)d_out;
+    sa.in_scale = fl.in_scale;
+    sa.mid_scale = fl.mid_scale;
+    sa.out_scale = fl.out_scale;
+    sa.tap_scale[0] = fl.tap_scale[0];
+    sa.tap_scale[1] = fl.tap_scale[1];
+    return launch_stream(p->fused_op, sa, fl.q, s);
+}
+
 }  // namespace
 
 extern "C" const char* gabor_status_string(gabor_status s)
@@ -297,10 +326,6 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
             // lead-in recomputation stays under a quarter of the J rows.
             const int L = 4 * q;
             fl.seg_rows = std::max(128, 4 * L);
-            if (const char* sr = std::getenv("LIBGABOR_SEG_ROWS")) {
-                const int v = std::atoi(sr);
-                if (v >= 16) fl.seg_rows = v / 16 * 16;
-            }
             if (fl.seg_rows > height) fl.seg_rows = (height + 15) / 16 * 16;
             if (p->fused_op == FUSED_F16 || p->fused_op == FUSED_F16X3) {
                 // float16 range: image scaled by 2^8 (|f| <= 128 stays below
@@ -478,26 +503,8 @@ extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int
         if (fl.fused) {
             LaunchTimer tm(p, ls, std::string(kFusedNames[p->fused_op]) + "_r" + std::to_string(p->freqs[i].R),
                            fl.macs, fl.bytes);
-            StreamArgs sa{};
-            sa.img = d_image;
-            sa.stride = row_stride_elems;
-            sa.H = p->H;
-            sa.W = p->W;
-            sa.boundary = p->boundary;
-            sa.R = p->freqs[i].R;
-            sa.seg_rows = fl.seg_rows;
-            sa.n_xs = (p->W + stream_strip_width() - 1) / stream_strip_width();
-            sa.n_ys = (p->H + fl.seg_rows - 1) / fl.seg_rows;
-            sa.n_jobs = fl.count;
-            sa.jobs = p->d_fjobs + fl.first;
-            sa.taps = p->d_taps;
-            sa.out = (float2*)d_out;
-            sa.in_scale = fl.in_scale;
-            sa.mid_scale = fl.mid_scale;
-            sa.out_scale = fl.out_scale;
-            sa.tap_scale[0] = fl.tap_scale[0];
-            sa.tap_scale[1] = fl.tap_scale[1];
-            if (launch_stream(p->fused_op, sa, fl.q, ls) != hipSuccess) return GABOR_ERR_DEVICE;
+            if (launch_fused_freq(p, i, d_image, row_stride_elems, d_out, fl.seg_rows, ls) != hipSuccess)
+                return GABOR_ERR_DEVICE;
         } else {
             LaunchTimer tm(p, ls, "col_fp32_r" + std::to_string(p->freqs[i].R), fl.macs, fl.bytes);
             if (launch_col_fp32(p->d_J, p->H, p->W, p->boundary, p->freqs[i], p->d_jobs + fl.first,
@@ -539,6 +546,84 @@ extern "C" gabor_status gabor_bank_apply_adjoint(gabor_plan p, const void* d_gra
                           p->d_taps, p->d_adjJ, d_grad_image, grad_row_stride_elems, stream) == hipSuccess
                ? GABOR_OK
                : GABOR_ERR_DEVICE;
+}
+
+// Segment heights the tuner tries for one fused launch: multiples of 16 up
+// to the image height.
+static std::vector<int> seg_candidates(int H, int q)
+{
+    const int hmax = (H + 15) / 16 * 16;
+    std::vector<int> c;
+    for (int v : {64, 128, 192, 256, 384, 512, 16 * q, 32 * q}) {
+        const int s = std::min(v, hmax);
+        if (s >= 16 && std::find(c.begin(), c.end(), s) == c.end()) c.push_back(s);
+    }
+    return c;
+}
+
+extern "C" gabor_status gabor_bank_autotune(gabor_plan p, const float* d_image, int64_t row_stride_elems,
+                                            void* d_out, int32_t reps, void* hip_stream)
+{
+    if (!p || !d_image || !d_out || reps < 1) return GABOR_ERR_INVALID_ARG;
+    if (row_stride_elems < p->W) return GABOR_ERR_INVALID_ARG;
+    if (!p->fjobs.empty() && (int64_t)(p->H - 1) * row_stride_elems + p->W >= (int64_t(1) << 30))
+        return GABOR_ERR_UNSUPPORTED;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess) return GABOR_ERR_DEVICE;
+    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return GABOR_ERR_DEVICE; }
+    gabor_status rc = GABOR_OK;
+    for (int i = 0; i < p->O && rc == GABOR_OK; ++i) {
+        FreqLaunch& fl = p->launches[i];
+        if (!fl.fused) continue;
+        double best = 1e30;
+        int best_seg = fl.seg_rows;
+        for (int seg : seg_candidates(p->H, fl.q)) {
+            // one untimed launch, then the median of reps timed launches
+            if (launch_fused_freq(p, i, d_image, row_stride_elems, d_out, seg, stream) != hipSuccess) { rc = GABOR_ERR_DEVICE; break; }
+            std::vector<float> t;
+            for (int r = 0; r < reps; ++r) {
+                float ms = 0.0f;
+                if (hipEventRecord(a, stream) != hipSuccess ||
+                    launch_fused_freq(p, i, d_image, row_stride_elems, d_out, seg, stream) != hipSuccess ||
+                    hipEventRecord(b, stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                    hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+                    rc = GABOR_ERR_DEVICE;
+                    break;
+                }
+                t.push_back(ms);
+            }
+            if (rc != GABOR_OK) break;
+            std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
+            if (t[t.size() / 2] < best) {
+                best = t[t.size() / 2];
+                best_seg = seg;
+            }
+        }
+        fl.seg_rows = best_seg;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return rc;
+}
+
+extern "C" gabor_status gabor_bank_get_tuning(gabor_plan p, int32_t* seg_rows, int32_t capacity, int32_t* n)
+{
+    if (!p || !n || capacity < 0 || (capacity > 0 && !seg_rows)) return GABOR_ERR_INVALID_ARG;
+    *n = p->O;
+    for (int i = 0; i < p->O && i < capacity; ++i) seg_rows[i] = p->launches[i].fused ? p->launches[i].seg_rows : 0;
+    return GABOR_OK;
+}
+
+extern "C" gabor_status gabor_bank_set_tuning(gabor_plan p, const int32_t* seg_rows, int32_t n)
+{
+    if (!p || !seg_rows || n != p->O) return GABOR_ERR_INVALID_ARG;
+    for (int i = 0; i < n; ++i)
+        if (p->launches[i].fused && (seg_rows[i] < 16 || seg_rows[i] % 16 != 0)) return GABOR_ERR_INVALID_ARG;
+    const int hmax = (p->H + 15) / 16 * 16;
+    for (int i = 0; i < n; ++i)
+        if (p->launches[i].fused) p->launches[i].seg_rows = std::min(seg_rows[i], hmax);
+    return GABOR_OK;
 }
 
 extern "C" gabor_status gabor_bank_destroy(gabor_plan p)

@@ -144,3 +144,11 @@ def test_batch_rejects_null_arguments():
     assert lib.gabor_batch_apply(None, None) == 1
     assert lib.gabor_batch_info(None, None, None) == 1
     assert lib.gabor_batch_destroy(None) == 0
+
+
+def test_tuning_rejects_null_arguments():
+    lib = binding.load()
+    n = ctypes.c_int32()
+    assert lib.gabor_bank_autotune(None, ctypes.c_void_p(16), 8, ctypes.c_void_p(16), 3, None) == 1
+    assert lib.gabor_bank_get_tuning(None, None, 0, ctypes.byref(n)) == 1
+    assert lib.gabor_bank_set_tuning(None, None, 0) == 1
