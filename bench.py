@@ -63,6 +63,9 @@ def parse():
                     help="approximate host time for the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default=",".join(FORMS))
+    ap.add_argument("--no-tune", action="store_true", help="keep the default segment heights")
+    ap.add_argument("--workloads", default="lsdft,batch,layer",
+                    help="secondary workloads reported under 'workloads' (lsdft, batch, layer; empty: none)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run a plain device-to-device copy of MIB MiB instead (counter calibration)")
     return ap.parse_args()
@@ -72,7 +75,7 @@ def precision_of(form: str) -> str:
     return "fp32" if form == "fp32_twopass" else form
 
 
-def time_form(binding, wl, img_dev, form, steps, warmup):
+def time_form(binding, wl, img_dev, form, steps, warmup, tune=True):
     import torch
     H, W = img_dev.shape
     if form == "fp32_twopass":
@@ -83,6 +86,7 @@ def time_form(binding, wl, img_dev, form, steps, warmup):
     finally:
         os.environ.pop("LIBGABOR_ALGO", None)
     out = torch.empty((len(wl.omegas), wl.n_orient, H, W), dtype=torch.complex64, device="cuda")
+    tuning = bank.autotune(img_dev, out, reps=3) if tune else bank.tuning
     for _ in range(warmup):
         bank(img_dev, out)
     torch.cuda.synchronize()
@@ -100,7 +104,7 @@ def time_form(binding, wl, img_dev, form, steps, warmup):
     info = bank.info
     res = out.cpu().numpy()
     bank.close()
-    return ms, prof, info, res
+    return ms, prof, info, res, tuning
 
 
 def compute_peak(form: str, kernel: str) -> tuple[str, float]:
@@ -160,6 +164,131 @@ def cpu_baseline(wl, img, target_s):
                       f"workload, FP64 direct Eq. (1), {t:.1f} s on {threads} threads"}, xs, ys, ref
 
 
+def event_time(fn, steps, warmup):
+    """Average milliseconds of fn() over steps calls, HIP events on the
+    current stream (every call here is one launch or a fixed launch group)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def hbm_roofline(nbytes, ms, note):
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None, "basis": note}
+
+
+def bench_lsdft(binding, workloads, steps, warmup):
+    """512^2 uniform image, 16 x 16 window, sigma 4, all 256 bins, zero
+    boundary: one lsdft_apply launch per step."""
+    import oracle
+    import torch
+    wl = workloads.lsdft_512()
+    img = torch.from_numpy(wl.image).cuda()
+    H, W = wl.image.shape
+    out = torch.empty((wl.my, wl.mx, H, W), dtype=torch.complex64, device="cuda")
+    macs, nbytes = binding.lsdft_work(H, W, wl.my, wl.mx)
+    xs, ys = workloads.sample_pixels(H, W, 300, 31)
+    ref = oracle.lsdft_points(wl.image, wl.my, wl.mx, wl.sigma, xs, ys, wl.boundary)
+    peak = np.abs(ref).max(0)
+    res = {"workload": wl.name, "outputs_per_call": wl.my * wl.mx * H * W, "forms": {}}
+    for form in ["fp32", "fp16_split", "bf16_split", "bf16", "fp16"]:
+        ms = event_time(lambda: binding.lsdft(img, wl.my, wl.mx, wl.sigma, wl.boundary, form, out=out),
+                        steps * 4, warmup)
+        got = out.cpu().numpy()[:, :, ys, xs].transpose(2, 0, 1)
+        res["forms"][form] = {"ms": round(ms, 5), "value": wl.my * wl.mx * H * W / (ms * 1e-3),
+                              "max_rel_err_per_bin": float((np.abs(got - ref).max(0) / peak).max()),
+                              "roofline": hbm_roofline(nbytes, ms, "one launch per call")}
+    res["unit"] = UNIT
+    res["algorithmic_bytes"] = nbytes
+    res["algorithmic_real_macs"] = macs
+    return res
+
+
+def bench_batch(binding, workloads, steps, warmup):
+    """256 uniform images, sides uniform in [64, 1024], 8 orientations x 5
+    frequencies pi/2 .. pi/32 (R up to 96), mirror: one gabor_batch_apply."""
+    import oracle
+    import torch
+    wl = workloads.bank_batch()
+    H = max(im.shape[0] for im in wl.images)
+    W = max(im.shape[1] for im in wl.images)
+    imgs = [torch.from_numpy(im).cuda() for im in wl.images]
+    n_out = sum(im.shape[0] * im.shape[1] for im in wl.images) * len(wl.omegas) * wl.n_orient
+    nbytes = sum(im.shape[0] * im.shape[1] for im in wl.images) * 4 + 8 * n_out
+    res = {"workload": wl.name, "images": len(imgs), "outputs_per_call": n_out, "unit": UNIT, "forms": {}}
+    for form in ["fp32", "bf16_split"]:
+        bank = binding.GaborBank(H, W, wl.omegas, wl.sigmas, wl.n_orient, None, 3.0, wl.boundary, form)
+        batch = binding.GaborBatch(bank, imgs)
+        ms = event_time(batch, steps, warmup)
+        n_launch, n_tiles = batch.info
+        worst = 0.0
+        for i in (0, len(imgs) // 2, len(imgs) - 1):
+            im = wl.images[i]
+            xs, ys = workloads.sample_pixels(im.shape[0], im.shape[1], 64, 40 + i)
+            ref = oracle.gabor_bank_points(im, wl.omegas, wl.sigmas, wl.thetas_or_default, xs, ys, 3.0,
+                                           wl.boundary)
+            got = batch.outputs[i].cpu().numpy()[:, :, ys, xs].transpose(2, 0, 1)
+            worst = max(worst, float((np.abs(got - ref).max(0) / np.abs(ref).max(0)).max()))
+        res["forms"][form] = {"ms": round(ms, 4), "value": n_out / (ms * 1e-3), "persistent_launches": n_launch,
+                              "tiles": n_tiles, "max_rel_err_sampled": worst,
+                              "roofline": hbm_roofline(nbytes, ms, "whole batch per call (several launches)")}
+        batch.close()
+        bank.close()
+        del batch
+        torch.cuda.empty_cache()
+    return res
+
+
+def bench_layer(binding, workloads, steps, warmup):
+    """Differentiable layer: 32 uniform 512^2 images, the 8 x 4 bank, zero
+    boundary; one forward and one backward (adjoint) of L = mean |F|^2."""
+    import oracle
+    import torch
+    from paper_1704_05231_amd.autograd import GaborLayer
+    wl = workloads.bank_layer()
+    x0 = torch.from_numpy(np.stack(wl.images)).cuda()
+    B, H, W = x0.shape
+    layer = GaborLayer(H, W, wl.omegas, wl.sigmas, wl.n_orient)
+
+    def step():
+        x = x0.detach().requires_grad_(True)
+        F = layer(x)
+        (F.real ** 2 + F.imag ** 2).mean().backward()
+        return x.grad
+
+    ms = event_time(step, steps, warmup)
+    g = step().cpu().numpy()
+    layer.bank.profile(True)
+    step()
+    prof = layer.bank.profile_read()
+    layer.bank.profile(False)
+    xs, ys = workloads.sample_pixels(H, W, 8, 55)
+    ref = oracle.gabor_grad_points(wl.images[0], wl.omegas, wl.sigmas, wl.thetas_or_default, xs, ys) / B
+    err = float(np.abs(g[0][ys, xs] - ref).max() / np.abs(ref).max())
+    adj = prof.get("adjoint_fp32")
+    adj_roof = None
+    if adj:
+        avg = adj["total_ms"] / adj["launches"]
+        tf = 2 * adj["real_macs"] / (avg * 1e-3) / 1e12
+        adj_roof = {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_TFLOPS["fp32_vector"],
+                    "unit": "TFLOP/s", "frac": round(tf / PEAK_TFLOPS["fp32_vector"], 4), "traffic": None,
+                    "launch_ms": round(avg, 5), "kernel": "adjoint_fp32 (row + column pass)"}
+    layer.close()
+    n_out = B * len(wl.omegas) * wl.n_orient * H * W
+    return {"workload": wl.name, "ms_forward_backward": round(ms, 4), "value": n_out / (ms * 1e-3),
+            "unit": "complex outputs/s (forward + backward)", "grad_max_rel_err_vs_oracle": err,
+            "adjoint_roofline": adj_roof}
+
+
 def calibrate_copy(mib: int, steps: int):
     import torch
     n = mib * 1024 * 1024 // 4
@@ -216,7 +345,8 @@ def main():
 
     forms, results = {}, {}
     for form in [f for f in args.forms.split(",") if f]:
-        ms, prof, info, res = time_form(binding, wl, img_dev, form, args.steps, args.warmup)
+        ms, prof, info, res, tuning = time_form(binding, wl, img_dev, form, args.steps, args.warmup,
+                                                not args.no_tune)
         results[form] = res
         forms[form] = {
             "value": n_out / (ms * 1e-3), "ms_per_step": round(ms, 5),
@@ -225,6 +355,7 @@ def main():
             "kernels": {k: {"launches": v["launches"], "avg_ms": round(v["total_ms"] / v["launches"], 5),
                             "real_macs": v["real_macs"], "bytes": v["bytes"]} for k, v in prof.items()},
             "real_macs_per_step": info.real_macs,
+            "segment_rows": tuning,
         }
 
     cpu = None
@@ -252,6 +383,13 @@ def main():
     }
     if "bf16_split" in forms and "fp32" in forms:
         line["bf16_split_vs_fp32"] = round(forms["bf16_split"]["value"] / forms["fp32"]["value"], 3)
+    extra = {}
+    for name in [w for w in args.workloads.split(",") if w]:
+        extra[name] = {"lsdft": bench_lsdft, "batch": bench_batch, "layer": bench_layer}[name](
+            binding, workloads, max(5, args.steps // 10), max(2, args.warmup // 5))
+        print(f"bench.py: {name} done", file=sys.stderr, flush=True)
+    if extra:
+        line["workloads"] = extra
     print(json.dumps(line), flush=True)
 
 
