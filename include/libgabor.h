@@ -152,10 +152,12 @@ gabor_status gabor_bank_apply_adjoint(gabor_plan plan, const void* d_grad_out, f
  *
  * gabor_batch_apply runs Algorithm 1 on every bound image: one persistent
  * launch per operand size of the fused kernel, each over the tiles of all
- * images, plus image-by-image FP32 two-pass launches for frequencies outside
- * the fused kernel's range (R > 56, or planes of 2^29 pixels and more).  It
- * allocates and copies nothing, so it may be captured in a HIP graph and
- * replayed; the images are read and the outputs written at each replay.
+ * images, plus FP32 two-pass launches over all images for frequencies
+ * outside the fused kernel's range (R > 56, or planes of 2^29 pixels and
+ * more; their intermediate planes live in a batch-owned workspace allocated
+ * by gabor_batch_create).  It allocates and copies nothing, so it may be
+ * captured in a HIP graph and replayed; the images are read and the outputs
+ * written at each replay.
  */
 typedef struct gabor_batch_s* gabor_batch;
 
@@ -223,8 +225,10 @@ gabor_status lsdft_work(int32_t height, int32_t width, int32_t m_y, int32_t m_x,
  * workgroup (a multiple of 16; each segment recomputes a lead-in of about 2R
  * rows of the horizontal pass).  gabor_bank_autotune times every candidate
  * segment height per fused frequency on the caller's image and output
- * buffers (d_out is overwritten), keeps the fastest median of `reps` timed
- * launches, and synchronises hip_stream.  get/set copy the chosen heights
+ * buffers (d_out is overwritten) and keeps the fastest median of `reps`
+ * timed launches; it then times whole applies with every height scaled by
+ * 1, 2 and 4 (the frequencies run concurrently) and keeps the fastest.  It
+ * synchronises hip_stream.  get/set copy the chosen heights
  * (n = number of frequencies; 0 for frequencies on the two-pass kernels) so
  * that a caller can cache them; set rejects heights that are not positive
  * multiples of 16.  Batches created afterwards use the new heights.

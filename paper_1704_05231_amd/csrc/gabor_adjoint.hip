@@ -73,22 +73,46 @@ __global__ __launch_bounds__(kAdjRowThreads) void k_adj_row(
 #pragma unroll
     for (int p = 0; p < P; ++p) re[p] = im[p] = 0.f;
     const int base = threadIdx.x * P;
-    if (jb.j_real) {
-        for (int T = 0; T < Kp; ++T) {
-            const float c = tc[T];
+    // Sliding register window: U taps per step over P + U staged samples of
+    // each signal (16-byte LDS reads; Kp and the segment are multiples of 4).
+    constexpr int U = kTapBlock;
+    auto win = [&](const float* sig, int T, float (&w)[P + U]) {
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                re[p] = fmaf(sA[base + p + T], c, re[p]);
-                im[p] = fmaf(sC[base + p + T], c, im[p]);
+        for (int j = 0; j < P + U; j += 4) {
+            const float4 v = *reinterpret_cast<const float4*>(sig + base + T + j);
+            w[j] = v.x; w[j + 1] = v.y; w[j + 2] = v.z; w[j + 3] = v.w;
+        }
+    };
+    if (jb.j_real) {
+        for (int T = 0; T < Kp; T += U) {
+            float wa[P + U], wc[P + U];
+            win(sA, T, wa);
+            win(sC, T, wc);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const float c = tc[T + u];
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    re[p] = fmaf(wa[p + u], c, re[p]);
+                    im[p] = fmaf(wc[p + u], c, im[p]);
+                }
             }
         }
     } else {
-        for (int T = 0; T < Kp; ++T) {
-            const float c = tc[T], d = td[T];
+        for (int T = 0; T < Kp; T += U) {
+            float wa[P + U], wb[P + U], wc[P + U], wd[P + U];
+            win(sA, T, wa);
+            win(sB, T, wb);
+            win(sC, T, wc);
+            win(sD, T, wd);
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                re[p] = fmaf(sA[base + p + T], c, fmaf(sB[base + p + T], d, re[p]));
-                im[p] = fmaf(sC[base + p + T], c, fmaf(sD[base + p + T], d, im[p]));
+            for (int u = 0; u < U; ++u) {
+                const float c = tc[T + u], d = td[T + u];
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    re[p] = fmaf(wa[p + u], c, fmaf(wb[p + u], d, re[p]));
+                    im[p] = fmaf(wc[p + u], c, fmaf(wd[p + u], d, im[p]));
+                }
             }
         }
     }
@@ -129,19 +153,30 @@ __global__ __launch_bounds__(kAdjColTX * (kAdjColTY / kAdjColP)) void k_adj_col(
         const float* tc = taps + jb.tap_off + 2 * Kp;        // col c
         const float* td = tc + Kp;                           // col d
         const float2* col = tile + (ty * P) * TX + tx;
+        // Sliding register window down the column: U taps per step.
+        constexpr int U = kTapBlock;
         if (jb.c_real) {
-            for (int T = 0; T < Kp; ++T) {
-                const float c = tc[T];
+            for (int T = 0; T < Kp; T += U) {
+                float w[P + U];
 #pragma unroll
-                for (int p = 0; p < P; ++p) acc[p] = fmaf(col[(p + T) * TX].x, c, acc[p]);
+                for (int j = 0; j < P + U; ++j) w[j] = col[(T + j) * TX].x;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const float c = tc[T + u];
+#pragma unroll
+                    for (int p = 0; p < P; ++p) acc[p] = fmaf(w[p + u], c, acc[p]);
+                }
             }
         } else {
-            for (int T = 0; T < Kp; ++T) {
-                const float c = tc[T], d = td[T];
+            for (int T = 0; T < Kp; T += U) {
+                float2 w[P + U];
 #pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    const float2 v = col[(p + T) * TX];
-                    acc[p] = fmaf(v.x, c, fmaf(-v.y, d, acc[p]));
+                for (int j = 0; j < P + U; ++j) w[j] = col[(T + j) * TX];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const float c = tc[T + u], d = td[T + u];
+#pragma unroll
+                    for (int p = 0; p < P; ++p) acc[p] = fmaf(w[p + u].x, c, fmaf(-w[p + u].y, d, acc[p]));
                 }
             }
         }

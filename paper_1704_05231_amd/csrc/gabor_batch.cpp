@@ -7,7 +7,8 @@
 // group is one persistent launch over the tiles (image, job, strip segment)
 // of every image, ordered by decreasing length so that the last round of
 // workgroups is short.  Frequencies outside the fused kernel's range run the
-// FP32 two-pass kernels image by image on the caller's stream.
+// FP32 two-pass kernels on the caller's stream, one launch per pass over all
+// images, each image with J planes of its own in a batch-owned workspace.
 #include <algorithm>
 #include <cstring>
 #include <new>
@@ -33,6 +34,8 @@ struct gabor_batch_s {
     std::vector<int> twopass_freqs;          // frequencies on the two-pass kernels
     BatchImage* d_images = nullptr;
     BatchFreq* d_freqs = nullptr;
+    float2* d_J = nullptr;                   // J planes of the two-pass frequencies, every image
+    int max_h = 0, max_w = 0;
     BatchTile* d_tiles = nullptr;
     int64_t tiles = 0;
 };
@@ -45,6 +48,7 @@ void batch_release(gabor_batch b)
     if (b->d_images) (void)hipFree(b->d_images);
     if (b->d_freqs) (void)hipFree(b->d_freqs);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_J) (void)hipFree(b->d_J);
     delete b;
 }
 
@@ -71,8 +75,13 @@ extern "C" gabor_status gabor_batch_create(gabor_batch* out, gabor_plan p, int32
     b->plan = p;
     b->n = n_images;
     const int sx = stream_strip_width();
+    int64_t J_elems = 0;
     for (int i = 0; i < n_images; ++i) {
         BatchImage im{};
+        im.J_off = J_elems;
+        J_elems += (int64_t)p->n_planes * heights[i] * widths[i];
+        b->max_h = std::max(b->max_h, (int)heights[i]);
+        b->max_w = std::max(b->max_w, (int)widths[i]);
         im.img = d_images[i];
         im.out = (float2*)d_outs[i];
         im.stride = row_strides[i];
@@ -144,6 +153,7 @@ extern "C" gabor_status gabor_batch_create(gabor_batch* out, gabor_plan p, int32
     const size_t ib = b->images.size() * sizeof(BatchImage), fb = freqs.size() * sizeof(BatchFreq);
     const size_t tb = std::max<size_t>(1, tiles.size()) * sizeof(BatchTile);
     hipError_t e = hipMalloc((void**)&b->d_images, ib);
+    if (e == hipSuccess && J_elems > 0) e = hipMalloc((void**)&b->d_J, (size_t)J_elems * sizeof(float2));
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_freqs, fb);
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_tiles, tb);
     if (e != hipSuccess) {
@@ -189,19 +199,27 @@ extern "C" gabor_status gabor_batch_apply(gabor_batch b, void* hip_stream)
         a.boundary = p->boundary;
         if (launch_batch(p->fused_op, a, g.q, ls) != hipSuccess) return GABOR_ERR_DEVICE;
     }
-    // Two-pass frequencies, image by image (they share the plan's J planes).
-    for (const BatchImage& im : b->images) {
-        for (size_t gi = 0; gi < p->row_groups.size(); ++gi) {
-            const RowGroup& rg = p->row_groups[gi];
-            if (launch_row_fp32(im.img, im.stride, im.H, im.W, p->boundary, p->freqs[rg.freq], rg, p->d_taps,
-                                p->d_J, stream) != hipSuccess)
-                return GABOR_ERR_DEVICE;
-        }
-        for (int f : b->twopass_freqs) {
-            const FreqLaunch& fl = p->launches[f];
-            if (launch_col_fp32(p->d_J, im.H, im.W, p->boundary, p->freqs[f], p->d_jobs + fl.first, fl.count,
-                                p->d_taps, im.out, stream) != hipSuccess)
-                return GABOR_ERR_DEVICE;
+    // Two-pass frequencies: every image in one launch per horizontal group
+    // and one per frequency (images in chunks that fit the grid), each image
+    // with its own J planes.
+    if (!b->twopass_freqs.empty()) {
+        int max_jobs = 1;
+        for (int f : b->twopass_freqs) max_jobs = std::max(max_jobs, p->launches[f].count);
+        const int chunk = std::max(1, std::min(65535, 65535 / max_jobs));
+        for (int i0 = 0; i0 < b->n; i0 += chunk) {
+            const int n = std::min(chunk, b->n - i0);
+            for (size_t gi = 0; gi < p->row_groups.size(); ++gi) {
+                const RowGroup& rg = p->row_groups[gi];
+                if (launch_row_fp32_batch(b->d_images + i0, n, b->max_h, b->max_w, p->boundary, p->freqs[rg.freq], rg,
+                                          p->d_taps, b->d_J, stream) != hipSuccess)
+                    return GABOR_ERR_DEVICE;
+            }
+            for (int f : b->twopass_freqs) {
+                const FreqLaunch& fl = p->launches[f];
+                if (launch_col_fp32_batch(b->d_images + i0, n, b->max_h, b->max_w, p->boundary, p->freqs[f],
+                                          p->d_jobs + fl.first, fl.count, p->d_taps, b->d_J, stream) != hipSuccess)
+                    return GABOR_ERR_DEVICE;
+            }
         }
     }
     if (fork) {

@@ -50,7 +50,8 @@ constexpr int kRowThreads = 256;
 template <int NC, int NR>
 __global__ __launch_bounds__(kRowThreads) void k_row_fp32(
     const float* __restrict__ img, int64_t stride, int H, int W, int boundary, int R, int Kp,
-    const float* __restrict__ taps, float2* __restrict__ J, int plane0)
+    const float* __restrict__ taps, float2* __restrict__ J, int plane0,
+    const BatchImage* __restrict__ bimg)
 {
     constexpr int P = kRowP, U = kRowU, NT = 2 * NC + NR;
     extern __shared__ float4 row_lds4[];
@@ -58,6 +59,15 @@ __global__ __launch_bounds__(kRowThreads) void k_row_fp32(
     const int seg = blockDim.x * P;
     const int x0 = blockIdx.x * seg;
     const int y = blockIdx.y;
+    if (bimg) {                                   // batched: this block's image
+        const BatchImage im = bimg[blockIdx.z];
+        img = im.img;
+        stride = im.stride;
+        H = im.H;
+        W = im.W;
+        J += im.J_off;
+        if (y >= H || x0 >= W) return;
+    }
     const float* src = img + (int64_t)y * stride;
     const int nload = seg + Kp;
     for (int i = threadIdx.x; i < nload; i += blockDim.x) {
@@ -157,11 +167,20 @@ __device__ __forceinline__ void col_tile(const float2* __restrict__ lds, const f
 
 __global__ __launch_bounds__(kColThreads) void k_col_fp32(
     const float2* __restrict__ J, int H, int W, int boundary, int R, int Kp,
-    const ColJob* __restrict__ jobs, const float* __restrict__ taps, float2* __restrict__ out)
+    const ColJob* __restrict__ jobs, int n_jobs, const float* __restrict__ taps, float2* __restrict__ out,
+    const BatchImage* __restrict__ bimg)
 {
     extern __shared__ float2 col_lds[];
-    const ColJob jb = jobs[blockIdx.z];
+    const ColJob jb = jobs[blockIdx.z % n_jobs];
     const int x0 = blockIdx.x * kColTX, y0 = blockIdx.y * kColTY;
+    if (bimg) {                                   // batched: this block's image
+        const BatchImage im = bimg[blockIdx.z / n_jobs];
+        J += im.J_off;
+        out = im.out;
+        H = im.H;
+        W = im.W;
+        if (y0 >= H || x0 >= W) return;
+    }
     const int lane = threadIdx.x % kColTX, grp = threadIdx.x / kColTX;
     const int64_t plane = (int64_t)H * W;
     const float2* src = J + (int64_t)jb.plane * plane;
@@ -212,7 +231,20 @@ hipError_t launch_row_t(const float* img, int64_t stride, int H, int W, int boun
     dim3 grid((W + seg - 1) / seg, H, 1);
     const size_t lds = sizeof(float) * (size_t)(seg + fd.Kp + 4);
     hipLaunchKernelGGL((k_row_fp32<NC, NR>), grid, dim3(threads), lds, stream, img, stride, H, W,
-                       boundary, fd.R, fd.Kp, d_taps + g.tap_off, d_J, g.plane0);
+                       boundary, fd.R, fd.Kp, d_taps + g.tap_off, d_J, g.plane0, (const BatchImage*)nullptr);
+    return hipGetLastError();
+}
+
+template <int NC, int NR>
+hipError_t launch_row_batch_t(const BatchImage* d_imgs, int n_images, int max_h, int max_w, int boundary,
+                              const FreqDesc& fd, const RowGroup& g, const float* d_taps, float2* d_J,
+                              hipStream_t stream)
+{
+    const int seg = kRowThreads * kRowP;
+    dim3 grid((max_w + seg - 1) / seg, max_h, n_images);
+    const size_t lds = sizeof(float) * (size_t)(seg + fd.Kp + 4);
+    hipLaunchKernelGGL((k_row_fp32<NC, NR>), grid, dim3(kRowThreads), lds, stream, (const float*)nullptr,
+                       (int64_t)0, 0, 0, boundary, fd.R, fd.Kp, d_taps + g.tap_off, d_J, g.plane0, d_imgs);
     return hipGetLastError();
 }
 
@@ -232,6 +264,39 @@ hipError_t launch_row_fp32(const float* img, int64_t stride, int H, int W, int b
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_row_fp32_batch(const BatchImage* d_imgs, int n_images, int max_h, int max_w, int boundary,
+                                 const FreqDesc& fd, const RowGroup& g, const float* d_taps, float2* d_J,
+                                 hipStream_t stream)
+{
+    if (n_images <= 0 || n_images > 65535 || max_h > 65535) return hipErrorInvalidValue;
+#define GABOR_ROW_CASE(NC, NR) \
+    if (g.n_cplx == NC && g.n_real == NR) return launch_row_batch_t<NC, NR>(d_imgs, n_images, max_h, max_w, boundary, fd, g, d_taps, d_J, stream);
+    GABOR_ROW_CASE(0, 1) GABOR_ROW_CASE(1, 0) GABOR_ROW_CASE(1, 1) GABOR_ROW_CASE(2, 0)
+    GABOR_ROW_CASE(2, 1) GABOR_ROW_CASE(3, 0) GABOR_ROW_CASE(3, 1) GABOR_ROW_CASE(4, 0)
+    GABOR_ROW_CASE(4, 1) GABOR_ROW_CASE(5, 0) GABOR_ROW_CASE(5, 1) GABOR_ROW_CASE(6, 0)
+    GABOR_ROW_CASE(6, 1)
+#undef GABOR_ROW_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_col_fp32_batch(const BatchImage* d_imgs, int n_images, int max_h, int max_w, int boundary,
+                                 const FreqDesc& fd, const ColJob* d_jobs, int n_jobs, const float* d_taps,
+                                 float2* d_J, hipStream_t stream)
+{
+    if (n_jobs <= 0) return hipSuccess;
+    if (n_images <= 0 || (long long)n_jobs * n_images > 65535) return hipErrorInvalidValue;
+    const size_t lds = sizeof(float2) * (size_t)(kColTY + fd.Kp) * kColTX;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_col_fp32,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    dim3 grid((max_w + kColTX - 1) / kColTX, (max_h + kColTY - 1) / kColTY, n_jobs * n_images);
+    hipLaunchKernelGGL(k_col_fp32, grid, dim3(kColThreads), lds, stream, (const float2*)d_J, 0, 0, boundary,
+                       fd.R, fd.Kp, d_jobs, n_jobs, d_taps, (float2*)nullptr, d_imgs);
+    return hipGetLastError();
+}
+
 hipError_t launch_col_fp32(const float2* d_J, int H, int W, int boundary, const FreqDesc& fd,
                            const ColJob* d_jobs, int n_jobs, const float* d_taps, float2* d_out,
                            hipStream_t stream)
@@ -245,7 +310,7 @@ hipError_t launch_col_fp32(const float2* d_J, int H, int W, int boundary, const 
     }
     dim3 grid((W + kColTX - 1) / kColTX, (H + kColTY - 1) / kColTY, n_jobs);
     hipLaunchKernelGGL(k_col_fp32, grid, dim3(kColThreads), lds, stream, d_J, H, W, boundary,
-                       fd.R, fd.Kp, d_jobs, d_taps, d_out);
+                       fd.R, fd.Kp, d_jobs, n_jobs, d_taps, d_out, (const BatchImage*)nullptr);
     return hipGetLastError();
 }
 

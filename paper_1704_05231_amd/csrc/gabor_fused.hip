@@ -170,17 +170,13 @@ __device__ __forceinline__ int fold_index(int i, int n, int boundary)
     return r < n ? r : p - r;
 }
 
-// Same mapping as fold_index without division: one reflection covers every
-// index within one image length of the edge, and the rare further
-// reflections (R larger than the image side) run in a loop, which keeps the
-// compiler from turning the uncommon path into straight-line code.
-__device__ __forceinline__ int fold_cheap(int i, int n, int boundary)
+// Same mapping for indices at most n - 1 outside [0, n): one reflection,
+// straight-line code.
+__device__ __forceinline__ int fold_once(int i, int n, int boundary)
 {
     if ((unsigned)i < (unsigned)n) return i;
     if (boundary == 0) return -1;
-    if (n == 1) return 0;
-    while ((unsigned)i >= (unsigned)n) i = i < 0 ? -i : 2 * (n - 1) - i;
-    return i;
+    return i < 0 ? -i : 2 * (n - 1) - i;
 }
 
 // Workgroup id remap: the hardware deals consecutive ids round-robin to the
@@ -310,7 +306,7 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
     }
 
     // ---- image slab staging, by column pairs: rows yseg - R + 16 b + i,
-    // columns x0 - R + c (lanes past the slab read nothing and write the
+    // columns xs0 + c (lanes past the slab read nothing and write the
     // padding rows).
     const __amdgpu_buffer_rsrc_t img_rsrc =
         make_rsrc(a.img, (uint32_t)(((int64_t)(a.H - 1) * a.stride + a.W) * 4));
@@ -318,7 +314,8 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
     // offset relative to the slab's first row when no row or column folds
     // (rel), and the LDS position.
     int col_of[2 * PER_T], rel[2 * PER_T], lds_at[PER_T], row_of[PER_T];
-    const bool cols_inside = x0 - R >= 0 && x0 - R + WF <= a.W;
+    const int xs0 = x0 - R;
+    const bool cols_inside = xs0 >= 0 && xs0 + WF <= a.W;
 #pragma unroll
     for (int k = 0; k < PER_T; ++k) {
         const int idx = tid + k * kThreads;
@@ -329,10 +326,13 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
         lds_at[k] = r * WP + c;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            col_of[2 * k + h] = live ? fold_index(x0 - R + c + h, a.W, a.boundary) : -1;
-            rel[2 * k + h] = live ? r * a.stride + (x0 - R + c + h) : -1;
+            col_of[2 * k + h] = live ? fold_index(xs0 + c + h, a.W, a.boundary) : -1;
+            rel[2 * k + h] = live ? r * a.stride + (xs0 + c + h) : -1;
         }
     }
+    // one reflection reaches every folded row when the band is shorter than
+    // the image; otherwise the general (division) form
+    const bool one_fold = 2 * R + 64 <= a.H;
     auto slab_load = [&](int b, float (&pre)[2 * PER_T]) {
         const int row0 = yseg - R + 16 * b;
         if (cols_inside && row0 >= 0 && row0 + 16 <= a.H) {
@@ -346,7 +346,8 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
         } else {
 #pragma unroll
             for (int k = 0; k < PER_T; ++k) {
-                const int yy = fold_cheap(row0 + row_of[k], a.H, a.boundary);
+                const int yy = one_fold ? fold_once(row0 + row_of[k], a.H, a.boundary)
+                                        : fold_index(row0 + row_of[k], a.H, a.boundary);
                 const uint32_t rowoff = (uint32_t)yy * (uint32_t)a.stride;
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {

@@ -78,6 +78,7 @@ struct BatchImage {
     const float* img;
     float2* out;               // [O][N][H][W] of this image
     int64_t stride;
+    int64_t J_off;             // first element of its J planes (two-pass frequencies)
     int32_t H, W, n_xs, pad_;
 };
 struct BatchFreq {
@@ -162,5 +163,16 @@ hipError_t launch_row_fp32(const float* img, int64_t stride, int H, int W, int b
 hipError_t launch_col_fp32(const float2* d_J, int H, int W, int boundary, const FreqDesc& fd,
                            const ColJob* d_jobs, int n_jobs, const float* d_taps,
                            float2* d_out, hipStream_t stream);
+
+// The same kernels over every image of a batch in one launch each: grid z
+// selects the image (and the job), H and W are the largest extents, and
+// blocks outside an image return at once.  Each image's J planes start at
+// its J_off in d_J; its outputs at its own pointer.
+hipError_t launch_row_fp32_batch(const BatchImage* d_imgs, int n_images, int max_h, int max_w, int boundary,
+                                 const FreqDesc& fd, const RowGroup& g, const float* d_taps, float2* d_J,
+                                 hipStream_t stream);
+hipError_t launch_col_fp32_batch(const BatchImage* d_imgs, int n_images, int max_h, int max_w, int boundary,
+                                 const FreqDesc& fd, const ColJob* d_jobs, int n_jobs, const float* d_taps,
+                                 float2* d_J, hipStream_t stream);
 
 }  // namespace gabor

@@ -602,6 +602,39 @@ extern "C" gabor_status gabor_bank_autotune(gabor_plan p, const float* d_image, 
         }
         fl.seg_rows = best_seg;
     }
+    // The frequencies run concurrently in an apply, where fewer, longer
+    // segments (less lead-in recomputation) can beat the per-launch optimum:
+    // time the whole apply with every segment scaled by 1, 2 and 4.
+    if (rc == GABOR_OK && !p->fjobs.empty()) {
+        std::vector<int> base_seg(p->O), best(p->O);
+        for (int i = 0; i < p->O; ++i) base_seg[i] = best[i] = p->launches[i].seg_rows;
+        const int hmax = (p->H + 15) / 16 * 16;
+        double best_t = 1e30;
+        for (int mult : {1, 2, 4}) {
+            for (int i = 0; i < p->O; ++i)
+                if (p->launches[i].fused) p->launches[i].seg_rows = std::min(base_seg[i] * mult, hmax);
+            std::vector<float> t;
+            for (int r = 0; r <= reps && rc == GABOR_OK; ++r) {
+                float ms = 0.0f;
+                if (hipEventRecord(a, stream) != hipSuccess ||
+                    gabor_bank_apply(p, d_image, row_stride_elems, d_out, hip_stream) != GABOR_OK ||
+                    hipEventRecord(b, stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                    hipEventElapsedTime(&ms, a, b) != hipSuccess)
+                    rc = GABOR_ERR_DEVICE;
+                else if (r > 0)
+                    t.push_back(ms);                       // the first apply is untimed
+            }
+            if (rc != GABOR_OK) break;
+            std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
+            // a scaled schedule must beat the per-launch optimum clearly
+            const double tm = t[t.size() / 2] * (mult == 1 ? 1.0 : 1.03);
+            if (tm < best_t) {
+                best_t = tm;
+                for (int i = 0; i < p->O; ++i) best[i] = p->launches[i].seg_rows;
+            }
+        }
+        for (int i = 0; i < p->O; ++i) p->launches[i].seg_rows = best[i];
+    }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     return rc;
