@@ -14,6 +14,10 @@ Functions:
   lsdft_points(img, my, mx, sigma, boundary, xs, ys) -> complex128 [P][My][Mx].
   gabor_grad_points(img, ..., xs, ys) -> float64 [P], gradient of
       mean |F|^2 over all bank outputs (zero boundary).
+  gabor_bank_iir(img, omegas, sigmas, thetas, boundary) -> complex128
+      [O][N][H][W], the recursive-smoother variant (modulate, third-order
+      recursive Gaussian forward and backward, demodulate), FP64.
+  iir_coeffs(sigma) -> (a0, a1, a2, a3) of that recursive Gaussian.
   gaussian_taps(sigma, R) -> float64 [2R+1], the normalised sampled Gaussian.
   radius(sigma, radius_sigmas) -> R = floor(radius_sigmas * sigma + 0.5).
 """
@@ -66,6 +70,10 @@ def _load():
     lib.oracle_lsdft_points.argtypes = [P, i32, i32, i64, i32, i32, f64, i32, i64, P, P, P, i32]
     lib.oracle_gabor_grad_points.argtypes = [P, i32, i32, i64, i32, P, P, i32, P, f64,
                                              i64, P, P, P, i32]
+    lib.oracle_gabor_bank_iir.argtypes = [P, i32, i32, i64, i32, P, P, i32, P, i32, P, i32]
+    lib.oracle_iir_coeffs.argtypes = [f64, P]
+    lib.oracle_iir_extension.argtypes = [f64]
+    lib.oracle_iir_extension.restype = ctypes.c_int
     lib.oracle_max_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -178,3 +186,25 @@ def gabor_grad_points(img, omegas, sigmas, thetas, xs, ys, radius_sigmas=3.0,
                                           _ptr(xs), _ptr(ys), _ptr(out), int(n_threads))
     _check(rc, "gabor_grad_points")
     return out
+
+
+def iir_coeffs(sigma: float):
+    """(a0, a1, a2, a3) of the recursive Gaussian: w[n] = a0 u[n] - a1 w[n-1] - ..."""
+    a = np.zeros(4)
+    _check(_load().oracle_iir_coeffs(float(sigma), _ptr(a)), "iir_coeffs")
+    return tuple(float(v) for v in a)
+
+
+def iir_extension(sigma: float) -> int:
+    return int(_load().oracle_iir_extension(float(sigma)))
+
+
+def gabor_bank_iir(img, omegas, sigmas, thetas, boundary="zero", n_threads: int = 0):
+    a = _img(img)
+    om, sg, th = _params(omegas, sigmas, thetas)
+    H, W = a.shape
+    out = np.empty((om.size, th.size, H, W, 2), dtype=np.float64)
+    rc = _load().oracle_gabor_bank_iir(_ptr(a), H, W, W, om.size, _ptr(om), _ptr(sg), th.size, _ptr(th),
+                                       _BOUNDARY[boundary], _ptr(out), int(n_threads))
+    _check(rc, "gabor_bank_iir")
+    return out[..., 0] + 1j * out[..., 1]

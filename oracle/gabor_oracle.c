@@ -18,6 +18,9 @@
  *   Localized SDFT -- Eq. (17) with the basis of Eq. (18), Sec. III-A.
  *   Gradient     -- d/df of L = mean |F|^2 over every bank output, from the
  *     chain rule applied to Eq. (1) (Sec. II); zero boundary only.
+ *   Recursive variant -- the paper's decomposition with a recursive
+ *     Gaussian smoother (an approximation of Eq. (1)), written out step by
+ *     step in the paper's order; see oracle_gabor_bank_iir.
  *
  * Readings of points the paper leaves open (each is also listed in the design
  * notes of the repository):
@@ -370,6 +373,174 @@ int oracle_gabor_grad_points(const float* img, int H, int W, int64_t stride,
             }
             free(kern);
         }
+    return ORACLE_OK;
+}
+
+/* ---------------------------------------------------------------------------
+ * Recursive (IIR) variant of the bank, Sec. II-A: the paper modulates the
+ * signal (Eq. (5)-(6) horizontally, Eq. (7)-(10) vertically), smooths with a
+ * recursive Gaussian filter whose cost per sample does not depend on sigma,
+ * and demodulates.  The smoother is the third-order recursive Gaussian of
+ * van Vliet, Young and Verbeek (ICPR 1998), which the paper adopts: a causal
+ * pass with poles 1/d and its anti-causal mirror, where d are the poles of
+ * the sigma = 2 design,
+ *   d1, d1* = 1.40098 +- 1.00236 i,   d3 = 1.85132,
+ * scaled to d^(1/q) with q chosen so that the variance of the cascade,
+ *   sum over the three poles of 2 d / (d - 1)^2,
+ * equals sigma^2 (bisection on q).  With (1 - z^-1/d1)(1 - z^-1/d1*)
+ * (1 - z^-1/d3) = 1 + a1 z^-1 + a2 z^-2 + a3 z^-3 and a0 = 1 + a1 + a2 + a3
+ * (unit DC gain):
+ *   forward  w[n] = a0 u[n] - a1 w[n-1] - a2 w[n-2] - a3 w[n-3]
+ *   backward v[n] = a0 w[n] - a1 v[n+1] - a2 v[n+2] - a3 v[n+3]
+ * Each line is extended by T = ceil(6 sigma) + 3 samples on both sides by
+ * the boundary rule (the recursion starts from rest at the far end of the
+ * extension); modulation uses the unfolded coordinate.  Per channel:
+ *   J(x,y) = exp(i wc x) IIR_x[ f_ext(k,y) exp(-i wc k) ](x)
+ *   F(x,y) = exp(i ws y) IIR_y[ J_ext(x,l) exp(-i ws l) ](y)
+ * with wc = w cos(theta), ws = w sin(theta); J_ext folds rows of J (the
+ * horizontal pass acts on each row alone).  The result approximates Eq. (1)
+ * with the untruncated Gaussian; it is judged against the direct sum by its
+ * signal-to-error ratio, and this function is the exact (FP64) reference for
+ * the GPU implementation of the same recursion.
+ */
+static double oracle_iir_variance(double q)
+{
+    const double dr = 1.40098, di = 1.00236, d3 = 1.85132;
+    /* d^(1/q) for the complex pole: modulus^(1/q), argument / q */
+    double mod = pow(sqrt(dr * dr + di * di), 1.0 / q), arg = atan2(di, dr) / q;
+    double cr = mod * cos(arg), ci = mod * sin(arg);
+    /* 2 d / (d - 1)^2 for d = cr + i ci, twice its real part for the pair */
+    double er = cr - 1.0, ei = ci;
+    double den_r = er * er - ei * ei, den_i = 2.0 * er * ei;     /* (d - 1)^2 */
+    double den2 = den_r * den_r + den_i * den_i;
+    double re = (2.0 * cr * den_r + 2.0 * ci * den_i) / den2;    /* Re 2d/(d-1)^2 */
+    double p3 = pow(d3, 1.0 / q);
+    return 2.0 * re + 2.0 * p3 / ((p3 - 1.0) * (p3 - 1.0));
+}
+
+int oracle_iir_coeffs(double sigma, double* a /* [4]: a0..a3 */)
+{
+    if (!(sigma >= 0.5) || !isfinite(sigma) || !a) return ORACLE_BAD_ARG;
+    double lo = 1e-3, hi = 1e4;
+    for (int it = 0; it < 200; ++it) {
+        double mid = sqrt(lo * hi);
+        if (oracle_iir_variance(mid) < sigma * sigma) lo = mid; else hi = mid;
+    }
+    double q = sqrt(lo * hi);
+    const double dr = 1.40098, di = 1.00236, d3 = 1.85132;
+    double mod = pow(sqrt(dr * dr + di * di), 1.0 / q), arg = atan2(di, dr) / q;
+    /* 1/d for the pair: (1/mod) e^{-i arg}; real pole 1/d3^(1/q) */
+    double pr = cos(arg) / mod, pi_ = -sin(arg) / mod, p3 = 1.0 / pow(d3, 1.0 / q);
+    /* (1 - p z^-1)(1 - p* z^-1) = 1 - 2 Re p z^-1 + |p|^2 z^-2, times (1 - p3 z^-1) */
+    double c1 = -2.0 * pr, c2 = pr * pr + pi_ * pi_;
+    a[1] = c1 - p3;
+    a[2] = c2 - c1 * p3;
+    a[3] = -c2 * p3;
+    a[0] = 1.0 + a[1] + a[2] + a[3];
+    return ORACLE_OK;
+}
+
+int oracle_iir_extension(double sigma)
+{
+    return (int)ceil(6.0 * sigma) + 3;
+}
+
+/* In place on n complex samples (re, im interleaved): forward then backward
+ * recursion, each from rest. */
+static void oracle_iir_line(double* z, int64_t n, const double* a)
+{
+    for (int c = 0; c < 2; ++c) {
+        double w1 = 0.0, w2 = 0.0, w3 = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            double w = a[0] * z[2 * i + c] - a[1] * w1 - a[2] * w2 - a[3] * w3;
+            z[2 * i + c] = w;
+            w3 = w2; w2 = w1; w1 = w;
+        }
+        w1 = w2 = w3 = 0.0;
+        for (int64_t i = n - 1; i >= 0; --i) {
+            double v = a[0] * z[2 * i + c] - a[1] * w1 - a[2] * w2 - a[3] * w3;
+            z[2 * i + c] = v;
+            w3 = w2; w2 = w1; w1 = v;
+        }
+    }
+}
+
+int oracle_gabor_bank_iir(const float* img, int H, int W, int64_t stride,
+                          int O, const double* omega, const double* sigma,
+                          int N, const double* theta, int boundary,
+                          double* out /* complex128 [O][N][H][W] */, int n_threads)
+{
+    int rc = oracle_check_bank(img, H, W, stride, O, omega, sigma, N, 0.0, boundary);
+    if (rc || !out) return rc ? rc : ORACLE_BAD_ARG;
+    for (int i = 0; i < O; ++i)
+        if (!(sigma[i] >= 0.5)) return ORACLE_BAD_ARG;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    int64_t plane = (int64_t)H * W;
+    double* J = (double*)malloc(sizeof(double) * 2 * plane);
+    if (!J) return ORACLE_NO_MEM;
+    for (int i = 0; i < O; ++i) {
+        double b[4];
+        oracle_iir_coeffs(sigma[i], b);
+        int64_t T = oracle_iir_extension(sigma[i]);
+        for (int k = 0; k < N; ++k) {
+            double th = oracle_theta(theta, k, N);
+            double wc = omega[i] * cos(th), ws = omega[i] * sin(th);
+            int bad = 0;
+            /* horizontal: rows */
+#pragma omp parallel for schedule(dynamic, 4)
+            for (int y = 0; y < H; ++y) {
+                int64_t n = W + 2 * T;
+                double* z = (double*)malloc(sizeof(double) * 2 * n);
+                if (!z) { bad = 1; continue; }
+                for (int64_t m = 0; m < n; ++m) {
+                    int64_t kx = m - T;
+                    double f = oracle_pixel(img, stride, H, W, kx, y, boundary);
+                    z[2 * m] = f * cos(wc * (double)kx);
+                    z[2 * m + 1] = -f * sin(wc * (double)kx);
+                }
+                oracle_iir_line(z, n, b);
+                for (int x = 0; x < W; ++x) {
+                    double re = z[2 * (x + T)], im = z[2 * (x + T) + 1];
+                    double c = cos(wc * (double)x), s = sin(wc * (double)x);
+                    J[2 * ((int64_t)y * W + x)] = re * c - im * s;
+                    J[2 * ((int64_t)y * W + x) + 1] = re * s + im * c;
+                }
+                free(z);
+            }
+            if (bad) { free(J); return ORACLE_NO_MEM; }
+            /* vertical: columns */
+            double* F = out + 2 * ((int64_t)i * N + k) * plane;
+#pragma omp parallel for schedule(dynamic, 4)
+            for (int x = 0; x < W; ++x) {
+                int64_t n = H + 2 * T;
+                double* z = (double*)malloc(sizeof(double) * 2 * n);
+                if (!z) { bad = 1; continue; }
+                for (int64_t m = 0; m < n; ++m) {
+                    int64_t ly = m - T;
+                    int64_t r = oracle_fold(ly, H, boundary);
+                    double jr = 0.0, ji = 0.0;
+                    if (r >= 0) { jr = J[2 * (r * W + x)]; ji = J[2 * (r * W + x) + 1]; }
+                    double c = cos(ws * (double)ly), s = sin(ws * (double)ly);
+                    z[2 * m] = jr * c + ji * s;           /* J exp(-i ws l) */
+                    z[2 * m + 1] = ji * c - jr * s;
+                }
+                oracle_iir_line(z, n, b);
+                for (int y = 0; y < H; ++y) {
+                    double re = z[2 * (y + T)], im = z[2 * (y + T) + 1];
+                    double c = cos(ws * (double)y), s = sin(ws * (double)y);
+                    F[2 * ((int64_t)y * W + x)] = re * c - im * s;
+                    F[2 * ((int64_t)y * W + x) + 1] = re * s + im * c;
+                }
+                free(z);
+            }
+            if (bad) { free(J); return ORACLE_NO_MEM; }
+        }
+    }
+    free(J);
     return ORACLE_OK;
 }
 
