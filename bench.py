@@ -64,8 +64,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default=",".join(FORMS))
     ap.add_argument("--no-tune", action="store_true", help="keep the default segment heights")
-    ap.add_argument("--workloads", default="lsdft,batch,layer",
-                    help="secondary workloads reported under 'workloads' (lsdft, batch, layer; empty: none)")
+    ap.add_argument("--workloads", default="lsdft,batch,layer,iir",
+                    help="secondary workloads reported under 'workloads' (lsdft, batch, layer, iir; empty: none)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run a plain device-to-device copy of MIB MiB instead (counter calibration)")
     return ap.parse_args()
@@ -289,6 +289,31 @@ def bench_layer(binding, workloads, steps, warmup):
             "adjoint_roofline": adj_roof}
 
 
+def bench_iir(binding, workloads, steps, warmup):
+    """The metric workload's bank with the recursive smoother (modulate,
+    third-order recursive Gaussian, demodulate; FP32): one gabor_bank_apply
+    of an IIR plan per step, and its signal-to-error ratio against the direct
+    Eq. (1) sum (Gaussian to 5 sigma) at sampled pixels."""
+    import oracle
+    import torch
+    wl = workloads.bank_1024()
+    img = wl.images[0]
+    H, W = img.shape
+    img_dev = torch.from_numpy(img).cuda()
+    bank = binding.GaborBank(H, W, wl.omegas, wl.sigmas, wl.n_orient, None, 3.0, wl.boundary, "fp32",
+                             smoother="iir")
+    out = torch.empty((len(wl.omegas), wl.n_orient, H, W), dtype=torch.complex64, device="cuda")
+    ms = event_time(lambda: bank(img_dev, out), steps, warmup)
+    xs, ys = workloads.sample_pixels(H, W, 200, 57)
+    ref = oracle.gabor_bank_points(img, wl.omegas, wl.sigmas, wl.thetas_or_default, xs, ys, 5.0, wl.boundary)
+    got = out.cpu().numpy()[:, :, ys, xs].transpose(2, 0, 1)
+    ser = 10 * np.log10((np.abs(ref) ** 2).sum(0) / (np.abs(got - ref) ** 2).sum(0))
+    bank.close()
+    n_out = len(wl.omegas) * wl.n_orient * H * W
+    return {"workload": wl.name + " (recursive smoother)", "ms": round(ms, 4), "value": n_out / (ms * 1e-3),
+            "unit": UNIT, "ser_db_min": round(float(ser.min()), 2), "ser_db_max": round(float(ser.max()), 2)}
+
+
 def calibrate_copy(mib: int, steps: int):
     import torch
     n = mib * 1024 * 1024 // 4
@@ -385,7 +410,7 @@ def main():
         line["bf16_split_vs_fp32"] = round(forms["bf16_split"]["value"] / forms["fp32"]["value"], 3)
     extra = {}
     for name in [w for w in args.workloads.split(",") if w]:
-        extra[name] = {"lsdft": bench_lsdft, "batch": bench_batch, "layer": bench_layer}[name](
+        extra[name] = {"lsdft": bench_lsdft, "batch": bench_batch, "layer": bench_layer, "iir": bench_iir}[name](
             binding, workloads, max(5, args.steps // 10), max(2, args.warmup // 5))
         print(f"bench.py: {name} done", file=sys.stderr, flush=True)
     if extra:

@@ -103,6 +103,27 @@ gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t width,
                              gabor_precision precision, void* hip_stream);
 
 /*
+ * gabor_bank_plan_iir -- the same bank with the paper's recursive smoother
+ * (Sec. II-A): each 1-D pass modulates by exp(-i w t), smooths with the
+ * third-order recursive Gaussian of van Vliet, Young and Verbeek (ICPR
+ * 1998; a causal pass and its anti-causal mirror, poles scaled so that the
+ * impulse response has variance sigma^2), and demodulates; the pi - theta
+ * partner reuses conj(J).  The cost per pixel does not depend on sigma; the
+ * result approximates Eq. (1) with the untruncated Gaussian (about 30 dB
+ * signal-to-error ratio), it is not the truncated FIR of gabor_bank_plan.
+ * Lines are extended by ceil(6 sigma) + 3 samples by the boundary rule.
+ * Arguments as for gabor_bank_plan (no truncation radius; FP32 arithmetic
+ * with FP64-reduced twiddles).  sigma below 0.5 returns
+ * GABOR_ERR_UNSUPPORTED.  The plan is applied with gabor_bank_apply; the
+ * adjoint and batches are not available for it (GABOR_ERR_UNSUPPORTED) and
+ * autotuning does nothing.
+ */
+gabor_status gabor_bank_plan_iir(gabor_plan* out, int32_t height, int32_t width,
+                                 int32_t n_freq, const double* omega, const double* sigma,
+                                 int32_t n_orient, const double* theta,
+                                 gabor_boundary boundary, void* hip_stream);
+
+/*
  * gabor_bank_apply -- run the bank on one image.
  *
  *   d_image           device FP32 image, height x width of the plan, row

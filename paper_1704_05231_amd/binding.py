@@ -28,7 +28,7 @@ BOUNDARY = {"zero": 0, "mirror": 1}
 PRECISION = {"fp32": 0, "bf16_split": 1, "fp16_split": 2, "bf16": 3, "fp16": 4}
 
 # Every symbol include/libgabor.h declares; the CPU tests check the exports.
-EXPORTS = ["gabor_status_string", "gabor_bank_plan", "gabor_bank_apply", "gabor_bank_apply_adjoint",
+EXPORTS = ["gabor_status_string", "gabor_bank_plan", "gabor_bank_plan_iir", "gabor_bank_apply", "gabor_bank_apply_adjoint",
            "gabor_bank_destroy", "gabor_batch_create", "gabor_batch_apply", "gabor_batch_info",
            "gabor_batch_destroy", "gabor_bank_autotune", "gabor_bank_get_tuning", "gabor_bank_set_tuning",
            "lsdft_apply", "lsdft_work", "gabor_bank_plan_info", "gabor_profile_enable",
@@ -75,6 +75,8 @@ def load():
     lib.gabor_bank_plan.argtypes = [ctypes.POINTER(P), i32, i32, i32, P, P, i32, P, f64,
                                     ctypes.c_int, ctypes.c_int, P]
     lib.gabor_bank_plan.restype = ctypes.c_int
+    lib.gabor_bank_plan_iir.argtypes = [ctypes.POINTER(P), i32, i32, i32, P, P, i32, P, ctypes.c_int, P]
+    lib.gabor_bank_plan_iir.restype = ctypes.c_int
     lib.gabor_bank_apply.argtypes = [P, P, i64, P, P]
     lib.gabor_bank_apply.restype = ctypes.c_int
     lib.gabor_bank_apply_adjoint.argtypes = [P, P, P, i64, P]
@@ -149,6 +151,20 @@ def gabor_bank_plan(height, width, omega, sigma, n_orient, theta=None, radius_si
                                 _p(sg), int(n_orient), _p(th), float(radius_sigmas),
                                 BOUNDARY[boundary], PRECISION[precision], _stream(stream))
     _check(st, "gabor_bank_plan")
+    return plan
+
+
+def gabor_bank_plan_iir(height, width, omega, sigma, n_orient, theta=None, boundary="zero",
+                        stream=None) -> ctypes.c_void_p:
+    om, sg, th = _f64(omega), _f64(sigma), _f64(theta)
+    if om.shape != sg.shape:
+        raise ValueError("omega and sigma must have the same length")
+    if th is not None and th.size != n_orient:
+        raise ValueError("theta must have n_orient entries")
+    plan = ctypes.c_void_p()
+    st = load().gabor_bank_plan_iir(ctypes.byref(plan), int(height), int(width), om.size, _p(om), _p(sg),
+                                    int(n_orient), _p(th), BOUNDARY[boundary], _stream(stream))
+    _check(st, "gabor_bank_plan_iir")
     return plan
 
 
@@ -279,7 +295,7 @@ class GaborBank:
     """
 
     def __init__(self, height, width, omegas, sigmas, n_orient=None, thetas=None,
-                 radius_sigmas=3.0, boundary="zero", precision="fp32"):
+                 radius_sigmas=3.0, boundary="zero", precision="fp32", smoother="fir"):
         if thetas is not None:
             thetas = _f64(thetas)
             n_orient = thetas.size if n_orient is None else n_orient
@@ -292,8 +308,14 @@ class GaborBank:
                        "n_orient": self.n_orient,
                        "thetas": None if thetas is None else [float(v) for v in thetas],
                        "radius_sigmas": float(radius_sigmas), "boundary": boundary, "precision": precision}
-        self._plan = gabor_bank_plan(height, width, omegas, sigmas, self.n_orient, thetas,
-                                     radius_sigmas, boundary, precision)
+        self.params["smoother"] = smoother
+        if smoother == "iir":
+            self._plan = gabor_bank_plan_iir(height, width, omegas, sigmas, self.n_orient, thetas, boundary)
+        elif smoother == "fir":
+            self._plan = gabor_bank_plan(height, width, omegas, sigmas, self.n_orient, thetas,
+                                         radius_sigmas, boundary, precision)
+        else:
+            raise ValueError("smoother must be 'fir' or 'iir'")
 
     @property
     def info(self) -> PlanInfo:

@@ -22,7 +22,8 @@ LIB = os.path.join(HERE, "libgabor.so")
 # arithmetic form so that its objects compile in parallel.
 SOURCES = ([("gabor_plan.cpp", [], "gabor_plan"), ("gabor_lsdft.cpp", [], "gabor_lsdft"),
             ("gabor_batch.cpp", [], "gabor_batch"),
-            ("gabor_fp32.hip", [], "gabor_fp32"), ("gabor_adjoint.hip", [], "gabor_adjoint")]
+            ("gabor_fp32.hip", [], "gabor_fp32"), ("gabor_adjoint.hip", [], "gabor_adjoint"),
+            ("gabor_iir.hip", [], "gabor_iir")]
            + [("gabor_fused.hip", [f"-DGABOR_FORM={k}"], f"gabor_fused_{k}") for k in range(5)])
 ARCH = "gfx950"
 

@@ -63,6 +63,7 @@ extern "C" gabor_status gabor_batch_create(gabor_batch* out, gabor_plan p, int32
     *out = nullptr;
     if (!p || n_images <= 0 || !d_images || !heights || !widths || !row_strides || !d_outs)
         return GABOR_ERR_INVALID_ARG;
+    if (p->iir) return GABOR_ERR_UNSUPPORTED;
     for (int i = 0; i < n_images; ++i) {
         if (!d_images[i] || !d_outs[i]) return GABOR_ERR_INVALID_ARG;
         if (heights[i] <= 0 || widths[i] <= 0 || heights[i] > p->H || widths[i] > p->W) return GABOR_ERR_INVALID_ARG;

@@ -154,6 +154,27 @@ hipError_t launch_adjoint(const float2* d_G, int H, int W, const AdjJob* d_jobs,
                           const float* d_taps, float2* d_J, float* d_grad, int64_t grad_stride,
                           hipStream_t stream);
 
+// Recursive-smoother variant (gabor_iir.hip): one recursion job runs a
+// causal and an anti-causal third-order recursion down every column of a
+// plane of n rows (lines extended by T rows on both sides by the boundary
+// rule), with modulation by exp(-i w l) before and demodulation by
+// exp(i w l) after, twiddles (cos, sin)(w l) at tw[tw_off + l + T].
+struct IirJob {
+    const void* in;            // float [n][in_stride] or float2 [n][in_stride]
+    float2* scratch;           // [n + 2T][cols] forward results
+    float2* out;               // [n][out_stride], or null: out_base plane out_plane
+    int64_t in_stride, out_stride;
+    int32_t in_complex, conj;  // input type; conjugate a complex input
+    int32_t n, cols, T, tw_off, out_plane, pad_;
+    float a[4];                // w[m] = a0 u[m] - a1 w[m-1] - a2 w[m-2] - a3 w[m-3]
+};
+// Transpose, horizontal jobs (on the transposed image, into d_JT planes
+// [W][H]), transpose back into d_J planes [H][W], vertical jobs (into the
+// output channels of d_out).
+hipError_t launch_iir(const float* d_image, int64_t stride, int H, int W, int boundary, float* d_fT,
+                      const IirJob* d_hjobs, int n_hjobs, float2* d_JT, float2* d_J, const IirJob* d_vjobs, int n_vjobs,
+                      const float2* d_tw, float2* d_out, hipStream_t stream);
+
 // Launchers (defined in gabor_fp32.hip).  They return the status of the
 // launch (hipGetLastError after enqueue).
 hipError_t launch_row_fp32(const float* img, int64_t stride, int H, int W, int boundary,

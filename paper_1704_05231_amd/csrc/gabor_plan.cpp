@@ -10,6 +10,7 @@
 //   - vertical jobs: one per horizontal result, producing theta and, when
 //     present, its partner pi - theta from the same J (Eq. (15)-(16)).
 #include <algorithm>
+#include <complex>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -64,6 +65,9 @@ void release(gabor_plan p)
     if (p->d_fjobs) (void)hipFree(p->d_fjobs);
     if (p->d_J) (void)hipFree(p->d_J);
     if (p->d_ajobs) (void)hipFree(p->d_ajobs);
+    for (void* q : {(void*)p->d_ihj, (void*)p->d_ivj, (void*)p->d_itw, (void*)p->d_ifT, (void*)p->d_iJT,
+                    (void*)p->d_iJ, (void*)p->d_iscr})
+        if (q) (void)hipFree(q);
     if (p->d_adjJ) (void)hipFree(p->d_adjJ);
     for (hipStream_t st : p->aux) (void)hipStreamDestroy(st);
     for (hipEvent_t e : p->fork_ev) (void)hipEventDestroy(e);
@@ -472,6 +476,199 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
     return GABOR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Recursive-smoother plan.  Coefficients of the third-order recursive
+// Gaussian (van Vliet, Young and Verbeek, ICPR 1998): poles of the sigma = 2
+// design, d1, d1* = 1.40098 +- 1.00236 i and d3 = 1.85132, scaled to d^(1/q)
+// with q chosen (bisection) so that the variance of the causal/anti-causal
+// cascade, the sum over the poles of 2 d / (d - 1)^2, equals sigma^2.
+namespace {
+
+double iir_cascade_variance(double q)
+{
+    const std::complex<double> d1(1.40098, 1.00236);
+    const double d3 = 1.85132;
+    const std::complex<double> p1 = std::pow(d1, 1.0 / q);
+    const double p3 = std::pow(d3, 1.0 / q);
+    const std::complex<double> t1 = 2.0 * p1 / ((p1 - 1.0) * (p1 - 1.0));
+    return 2.0 * t1.real() + 2.0 * p3 / ((p3 - 1.0) * (p3 - 1.0));
+}
+
+// a[0..3] of w[m] = a0 u[m] - a1 w[m-1] - a2 w[m-2] - a3 w[m-3]
+void iir_coefficients(double sigma, double* a)
+{
+    double lo = 1e-3, hi = 1e4;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = std::sqrt(lo * hi);
+        if (iir_cascade_variance(mid) < sigma * sigma) lo = mid;
+        else hi = mid;
+    }
+    const double q = std::sqrt(lo * hi);
+    const std::complex<double> r1 = 1.0 / std::pow(std::complex<double>(1.40098, 1.00236), 1.0 / q);
+    const double r3 = 1.0 / std::pow(1.85132, 1.0 / q);
+    // (1 - r1 z^-1)(1 - conj(r1) z^-1)(1 - r3 z^-1) = 1 + a1 z^-1 + a2 z^-2 + a3 z^-3
+    const double c1 = -2.0 * r1.real(), c2 = std::norm(r1);
+    a[1] = c1 - r3;
+    a[2] = c2 - c1 * r3;
+    a[3] = -c2 * r3;
+    a[0] = 1.0 + a[1] + a[2] + a[3];
+}
+
+// (cos, sin)(w l) for l = -T .. n + T - 1, the phase reduced in FP64
+void push_twiddles(std::vector<float2>& tw, double w, int n, int T)
+{
+    const double two_pi = 2.0 * kPi;
+    for (int l = -T; l < n + T; ++l) {
+        double ph = std::fmod(w * (double)l, two_pi);
+        double c, s;
+        exact_cos_sin(ph, &c, &s);
+        tw.push_back(make_float2((float)c, (float)s));
+    }
+}
+
+}  // namespace
+
+extern "C" gabor_status gabor_bank_plan_iir(gabor_plan* out, int32_t height, int32_t width, int32_t n_freq,
+                                            const double* omega, const double* sigma, int32_t n_orient,
+                                            const double* theta, gabor_boundary boundary, void* hip_stream)
+{
+    if (!out) return GABOR_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (height <= 0 || width <= 0 || n_freq <= 0 || n_orient <= 0 || !omega || !sigma) return GABOR_ERR_INVALID_ARG;
+    if (boundary != GABOR_BOUNDARY_ZERO && boundary != GABOR_BOUNDARY_MIRROR) return GABOR_ERR_INVALID_ARG;
+    for (int i = 0; i < n_freq; ++i)
+        if (!std::isfinite(omega[i]) || !std::isfinite(sigma[i]) || !(sigma[i] > 0.0)) return GABOR_ERR_INVALID_ARG;
+    if (theta)
+        for (int k = 0; k < n_orient; ++k)
+            if (!std::isfinite(theta[k])) return GABOR_ERR_INVALID_ARG;
+    if (height > 65535 || width > 65535) return GABOR_ERR_UNSUPPORTED;
+    for (int i = 0; i < n_freq; ++i)
+        if (sigma[i] < 0.5 || sigma[i] > 1000.0) return GABOR_ERR_UNSUPPORTED;
+    gabor_plan p = new (std::nothrow) gabor_plan_s;
+    if (!p) return GABOR_ERR_OUT_OF_MEMORY;
+    p->iir = true;
+    p->H = height;
+    p->W = width;
+    p->O = n_freq;
+    p->N = n_orient;
+    p->boundary = boundary;
+    p->precision = GABOR_PREC_FP32;
+    const int64_t npix = (int64_t)height * width;
+    std::vector<double> cs(n_orient), sn(n_orient);
+    for (int k = 0; k < n_orient; ++k) {
+        const double th = theta ? theta[k] : kPi * (double)k / (double)n_orient;
+        exact_cos_sin(th, &cs[k], &sn[k]);
+    }
+    std::vector<IirJob> hj, vj;
+    std::vector<float2> tw;
+    std::vector<int> h_of_v;                                  // horizontal job feeding each vertical job
+    int64_t h_scr = 0, v_scr = 0;
+    for (int i = 0; i < n_freq; ++i) {
+        double a[4];
+        iir_coefficients(sigma[i], a);
+        const int T = (int)std::ceil(6.0 * sigma[i]) + 3;
+        FreqDesc fd{};
+        fd.R = T;
+        fd.K = 2 * T + 1;
+        fd.Kp = fd.K;
+        p->freqs.push_back(fd);
+        std::vector<char> used(n_orient, 0);
+        for (int n = 0; n < n_orient; ++n) {
+            if (used[n]) continue;
+            used[n] = 1;
+            int partner = -1;
+            for (int m = n + 1; m < n_orient && !(omega[i] * cs[n] == 0.0); ++m)
+                if (!used[m] && std::fabs(cs[m] + cs[n]) < kPairTol && std::fabs(sn[m] - sn[n]) < kPairTol) {
+                    partner = m;
+                    used[m] = 1;
+                    break;
+                }
+            IirJob h{};
+            h.in_complex = 0;
+            h.n = width;
+            h.cols = height;
+            h.T = T;
+            h.in_stride = height;
+            h.out_stride = height;
+            h.tw_off = (int)tw.size();
+            for (int c = 0; c < 4; ++c) h.a[c] = (float)a[c];
+            push_twiddles(tw, omega[i] * cs[n], width, T);
+            h_scr += (int64_t)(width + 2 * T) * height;
+            const int hidx = (int)hj.size();
+            hj.push_back(h);
+            const int vtw = (int)tw.size();
+            push_twiddles(tw, omega[i] * sn[n], height, T);
+            for (int side = 0; side < (partner >= 0 ? 2 : 1); ++side) {
+                IirJob v{};
+                v.in_complex = 1;
+                v.conj = side;
+                v.n = height;
+                v.cols = width;
+                v.T = T;
+                v.in_stride = width;
+                v.out_stride = width;
+                v.tw_off = vtw;
+                v.out_plane = i * n_orient + (side ? partner : n);
+                for (int c = 0; c < 4; ++c) v.a[c] = (float)a[c];
+                v_scr += (int64_t)(height + 2 * T) * width;
+                vj.push_back(v);
+                h_of_v.push_back(hidx);
+            }
+            p->n_row_passes += 1;
+            p->n_col_passes += partner >= 0 ? 2 : 1;
+            p->row_macs += 16 * npix;                       // two real recursions of 4 taps, each way
+            p->col_macs += (int64_t)(partner >= 0 ? 2 : 1) * 16 * npix;
+        }
+    }
+    p->n_ihj = (int)hj.size();
+    p->n_ivj = (int)vj.size();
+    const size_t scr = (size_t)std::max(h_scr, v_scr) * sizeof(float2);
+    const size_t plane2 = (size_t)npix * sizeof(float2);
+    p->workspace_bytes = (int64_t)(scr + 2 * hj.size() * plane2 + npix * sizeof(float) + tw.size() * sizeof(float2) +
+                                   (hj.size() + vj.size()) * sizeof(IirJob));
+    if (env_flag("LIBGABOR_FAIL_ALLOC")) {
+        release(p);
+        return GABOR_ERR_OUT_OF_MEMORY;
+    }
+    hipError_t e = hipMalloc((void**)&p->d_iscr, scr);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_iJT, hj.size() * plane2);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_iJ, hj.size() * plane2);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_ifT, npix * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_itw, tw.size() * sizeof(float2));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_ihj, hj.size() * sizeof(IirJob));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_ivj, vj.size() * sizeof(IirJob));
+    if (e != hipSuccess) {
+        release(p);
+        return e == hipErrorOutOfMemory ? GABOR_ERR_OUT_OF_MEMORY : GABOR_ERR_DEVICE;
+    }
+    // device pointers of the job tables: scratch slices, transposed and
+    // straight J planes
+    int64_t off = 0;
+    for (size_t j = 0; j < hj.size(); ++j) {
+        hj[j].in = p->d_ifT;
+        hj[j].scratch = p->d_iscr + off;
+        hj[j].out = p->d_iJT + (int64_t)j * npix;
+        off += (int64_t)(hj[j].n + 2 * hj[j].T) * hj[j].cols;
+    }
+    off = 0;
+    for (size_t j = 0; j < vj.size(); ++j) {
+        vj[j].in = p->d_iJ + (int64_t)h_of_v[j] * npix;
+        vj[j].scratch = p->d_iscr + off;
+        vj[j].out = nullptr;
+        off += (int64_t)(vj[j].n + 2 * vj[j].T) * vj[j].cols;
+    }
+    hipStream_t stream = (hipStream_t)hip_stream;
+    if (hipMemcpyAsync(p->d_itw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(p->d_ihj, hj.data(), hj.size() * sizeof(IirJob), hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(p->d_ivj, vj.data(), vj.size() * sizeof(IirJob), hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+        release(p);
+        return GABOR_ERR_DEVICE;
+    }
+    *out = p;
+    return GABOR_OK;
+}
+
 extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int64_t row_stride_elems,
                                          void* d_out, void* hip_stream)
 {
@@ -480,6 +677,14 @@ extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int
     if (!p->fjobs.empty() && (int64_t)(p->H - 1) * row_stride_elems + p->W >= (int64_t(1) << 30))
         return GABOR_ERR_UNSUPPORTED;   // image span past the 32-bit buffer offsets of the fused kernel
     hipStream_t stream = (hipStream_t)hip_stream;
+    if (p->iir) {
+        const int64_t npix = (int64_t)p->H * p->W;
+        LaunchTimer tm(p, stream, "iir_fp32", p->row_macs + p->col_macs, 4 * npix + 8 * (int64_t)p->O * p->N * npix);
+        return launch_iir(d_image, row_stride_elems, p->H, p->W, p->boundary, p->d_ifT, p->d_ihj, p->n_ihj, p->d_iJT,
+                          p->d_iJ, p->d_ivj, p->n_ivj, p->d_itw, (float2*)d_out, stream) == hipSuccess
+                   ? GABOR_OK
+                   : GABOR_ERR_DEVICE;
+    }
     for (size_t gi = 0; gi < p->row_groups.size(); ++gi) {
         const RowGroup& g = p->row_groups[gi];
         const int64_t npix = (int64_t)p->H * p->W;
@@ -525,7 +730,7 @@ extern "C" gabor_status gabor_bank_apply_adjoint(gabor_plan p, const void* d_gra
 {
     if (!p || !d_grad_out || !d_grad_image) return GABOR_ERR_INVALID_ARG;
     if (grad_row_stride_elems < p->W) return GABOR_ERR_INVALID_ARG;
-    if (p->boundary != GABOR_BOUNDARY_ZERO) return GABOR_ERR_UNSUPPORTED;
+    if (p->boundary != GABOR_BOUNDARY_ZERO || p->iir) return GABOR_ERR_UNSUPPORTED;
     if (adj_row_lds_bytes(p->adj_max_kp) > 160 * 1024 || adj_col_lds_bytes(p->adj_max_kp) > 160 * 1024)
         return GABOR_ERR_UNSUPPORTED;
     const int64_t npix = (int64_t)p->H * p->W;
@@ -566,6 +771,7 @@ extern "C" gabor_status gabor_bank_autotune(gabor_plan p, const float* d_image, 
 {
     if (!p || !d_image || !d_out || reps < 1) return GABOR_ERR_INVALID_ARG;
     if (row_stride_elems < p->W) return GABOR_ERR_INVALID_ARG;
+    if (p->iir) return GABOR_OK;                                 // nothing to tune
     if (!p->fjobs.empty() && (int64_t)(p->H - 1) * row_stride_elems + p->W >= (int64_t(1) << 30))
         return GABOR_ERR_UNSUPPORTED;
     hipStream_t stream = (hipStream_t)hip_stream;

@@ -43,6 +43,16 @@ struct gabor_plan_s {
     int64_t adj_row_macs = 0, adj_col_macs = 0;
     AdjJob* d_ajobs = nullptr;
     float2* d_adjJ = nullptr;              // adjoint workspace, allocated by the first adjoint call
+    // recursive-smoother variant (gabor_bank_plan_iir)
+    bool iir = false;
+    int32_t n_ihj = 0, n_ivj = 0;
+    IirJob* d_ihj = nullptr;
+    IirJob* d_ivj = nullptr;
+    float2* d_itw = nullptr;
+    float* d_ifT = nullptr;
+    float2* d_iJT = nullptr;
+    float2* d_iJ = nullptr;
+    float2* d_iscr = nullptr;
     int fused_op = FUSED_F32;
     int32_t n_planes = 0;
     int32_t n_row_passes = 0, n_col_passes = 0;

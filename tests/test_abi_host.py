@@ -152,3 +152,17 @@ def test_tuning_rejects_null_arguments():
     assert lib.gabor_bank_autotune(None, ctypes.c_void_p(16), 8, ctypes.c_void_p(16), 3, None) == 1
     assert lib.gabor_bank_get_tuning(None, None, 0, ctypes.byref(n)) == 1
     assert lib.gabor_bank_set_tuning(None, None, 0) == 1
+
+
+def test_iir_plan_rejects_bad_arguments():
+    lib = binding.load()
+    om, sg = np.array([1.0]), np.array([2.0])
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    plan = ctypes.c_void_p(7)
+    assert lib.gabor_bank_plan_iir(None, 8, 8, 1, P(om), P(sg), 4, None, 0, None) == 1
+    assert lib.gabor_bank_plan_iir(ctypes.byref(plan), 0, 8, 1, P(om), P(sg), 4, None, 0, None) == 1
+    assert plan.value is None
+    assert lib.gabor_bank_plan_iir(ctypes.byref(plan), 8, 8, 1, P(om), P(np.array([-1.0])), 4, None, 0, None) == 1
+    assert lib.gabor_bank_plan_iir(ctypes.byref(plan), 8, 8, 1, P(om), P(sg), 4, None, 3, None) == 1
+    # sigma below the recursive design's range: valid but unsupported, before any allocation
+    assert lib.gabor_bank_plan_iir(ctypes.byref(plan), 8, 8, 1, P(om), P(np.array([0.3])), 4, None, 0, None) == 4
