@@ -87,8 +87,8 @@ const char* gabor_status_string(gabor_status status);
  *   radius_sigmas  truncation of S in units of sigma (3.0 gives R = 3 sigma).
  *   boundary       rule for samples outside the image.
  *   precision      arithmetic of the Gaussian contractions.  Frequencies the
- *                  fused kernel cannot take (R > 56, or planes of 2^29 pixels
- *                  and more) run the FP32 two-pass kernels whatever the
+ *                  fused kernel cannot take (R > 56, or planes of more than
+ *                  2^27 pixels) run the FP32 two-pass kernels whatever the
  *                  precision.
  *   hip_stream     stream used to upload the plan's tables.
  *
@@ -174,8 +174,8 @@ gabor_status gabor_bank_apply_adjoint(gabor_plan plan, const void* d_grad_out, f
  * gabor_batch_apply runs Algorithm 1 on every bound image: one persistent
  * launch per operand size of the fused kernel, each over the tiles of all
  * images, plus FP32 two-pass launches over all images for frequencies
- * outside the fused kernel's range (R > 56, or planes of 2^29 pixels and
- * more; their intermediate planes live in a batch-owned workspace allocated
+ * outside the fused kernel's range (R > 56, or planes of more than 2^27
+ * pixels; their intermediate planes live in a batch-owned workspace allocated
  * by gabor_batch_create).  It allocates and copies nothing, so it may be
  * captured in a HIP graph and replayed; the images are read and the outputs
  * written at each replay.
@@ -223,7 +223,7 @@ gabor_status gabor_bank_destroy(gabor_plan plan);
  *
  * One kernel launch on hip_stream; the call allocates nothing (the window
  * and twiddle tables travel as launch arguments), so it may be captured in
- * a HIP graph.  Images of 2^29 pixels or more, or whose row span reaches
+ * a HIP graph.  Images of more than 2^27 pixels, or whose row span reaches
  * 2^30 elements, return GABOR_ERR_UNSUPPORTED.
  */
 gabor_status lsdft_apply(const float* d_image, int32_t height, int32_t width,
@@ -252,7 +252,7 @@ gabor_status lsdft_work(int32_t height, int32_t width, int32_t m_y, int32_t m_x,
  * synchronises hip_stream.  get/set copy the chosen heights
  * (n = number of frequencies; 0 for frequencies on the two-pass kernels) so
  * that a caller can cache them; set rejects heights that are not positive
- * multiples of 16.  Batches created afterwards use the new heights.
+ * multiples of 32.  Batches created afterwards use the new heights.
  */
 gabor_status gabor_bank_autotune(gabor_plan plan, const float* d_image, int64_t row_stride_elems,
                                  void* d_out, int32_t reps, void* hip_stream);

@@ -202,6 +202,7 @@ __device__ __forceinline__ void lds_barrier()
 // instruction and the outstanding-access counts stay static.
 typedef int i2_t __attribute__((ext_vector_type(2)));
 constexpr uint32_t kOutside = 0xFFFFFFF0u;   // an offset past every resource
+constexpr uint32_t kFar = 0xC0000000u;       // past every output plane of at most 2^30 bytes
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes)
 {
@@ -313,7 +314,10 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
     // Per thread and pair k: the folded columns (fixed for the strip), the
     // offset relative to the slab's first row when no row or column folds
     // (rel), and the LDS position.
-    int col_of[2 * PER_T], rel[2 * PER_T], lds_at[PER_T], row_of[PER_T];
+    // rel4: byte offset from the slab's first row; lanes past the slab read
+    // the first element (their values land in padding rows and are never used)
+    int col_of[2 * PER_T], lds_at[PER_T], row_of[PER_T];
+    uint32_t rel4[2 * PER_T];
     const int xs0 = x0 - R;
     const bool cols_inside = xs0 >= 0 && xs0 + WF <= a.W;
 #pragma unroll
@@ -327,7 +331,7 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             col_of[2 * k + h] = live ? fold_index(xs0 + c + h, a.W, a.boundary) : -1;
-            rel[2 * k + h] = live ? r * a.stride + (xs0 + c + h) : -1;
+            rel4[2 * k + h] = live ? (uint32_t)(r * a.stride + (xs0 + c + h)) * 4u : 0u;
         }
     }
     // one reflection reaches every folded row when the band is shorter than
@@ -337,12 +341,10 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
         const int row0 = yseg - R + 16 * b;
         if (cols_inside && row0 >= 0 && row0 + 16 <= a.H) {
             // interior: no folding, one add per element
-            const uint32_t base = (uint32_t)row0 * (uint32_t)a.stride;
+            const uint32_t base4 = (uint32_t)row0 * (uint32_t)a.stride * 4u;
 #pragma unroll
-            for (int k = 0; k < 2 * PER_T; ++k) {
-                const uint32_t off = rel[k] >= 0 ? (base + (uint32_t)rel[k]) * 4u : kOutside;
-                pre[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(img_rsrc, (int)off, 0, 0));
-            }
+            for (int k = 0; k < 2 * PER_T; ++k)
+                pre[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(img_rsrc, (int)(base4 + rel4[k]), 0, 0));
         } else {
 #pragma unroll
             for (int k = 0; k < PER_T; ++k) {
@@ -427,7 +429,17 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
         ? make_rsrc(a.out + (int64_t)jb.out_c * plane, plane_bytes) : make_rsrc(a.out, 0u);
     const __amdgpu_buffer_rsrc_t out_d = LS && jb.out_d >= 0
         ? make_rsrc(a.out + (int64_t)jb.out_d * plane, plane_bytes) : make_rsrc(a.out, 0u);
-    const int yend = min(a.H, yseg + a.seg_rows);
+    // Output offsets: a per-lane base plus a wave-uniform row term.  Rows past
+    // the segment end are written only in the last step of an odd step
+    // count, which happens only where the segment reaches the image bottom
+    // (segments are multiples of 32 rows or cover the image), so those rows
+    // lie past the plane and the range check drops them.  Columns past the
+    // image (last strip only) start at kFar, above every plane of at most
+    // 2^30 bytes and far enough from 2^32 that adding a segment's rows cannot
+    // wrap.
+    const uint32_t W8 = (uint32_t)a.W * 8u;
+    const int xcol = x0 + 16 * w + o;
+    const uint32_t lane_off = xcol < a.W ? ((uint32_t)(yseg + 4 * g) * (uint32_t)a.W + (uint32_t)xcol) * 8u : kFar;
     auto col_pass = [&](int s) {
         Pack bah[NP], bal[NP], bbh[NP], bbl[NP];
         const T* base = Jst + (16 * w + o) * RP;
@@ -455,11 +467,9 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
             }
         }
         if constexpr (F::drain) f32_mfma_drain(P1, P2, P3, P4);
-        const int x = x0 + 16 * w + o;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int y = yseg + 16 * s + 4 * g + r;
-            const uint32_t off = (x < a.W && y < yend) ? (uint32_t)(((int64_t)y * a.W + x) * 8) : kOutside;
+            const uint32_t off = lane_off + (uint32_t)(16 * s + r) * W8;
             const float p1 = sc(P1[r], out_s), p2 = sc(P2[r], out_s);
             const float p3 = sc(P3[r], out_s), p4 = sc(P4[r], out_s);
             i2_t va, vb;
@@ -522,6 +532,16 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
         step(s, s_next, s_lead);
         step(s + 1, s_lead, s_next);
     }
+}
+
+// Launch conditions the kernel relies on: segments of a multiple of 32 rows
+// (or one segment over the whole image), a band that fits the quarter, and
+// output planes of at most 2^30 bytes.
+inline bool stream_args_ok(const StreamArgs& a, int Q)
+{
+    if (a.seg_rows <= 0 || a.seg_rows % 16 != 0 || (a.seg_rows % 32 != 0 && a.seg_rows < a.H)) return false;
+    if (16 + 2 * a.R > 4 * Q || Q > kStreamMaxQuarter) return false;
+    return (int64_t)a.H * a.W * 8 <= (int64_t(1) << 30);
 }
 
 template <int OP, int Q>
@@ -758,7 +778,7 @@ hipError_t launch_lsdft(int op, const StreamArgs& a, const LsdftTaps& t, int Q, 
     if (t.m[0] < 1 || t.m[0] > kLsdftMaxM || t.m[1] < 1 || t.m[1] > kLsdftMaxM) return hipErrorInvalidValue;
     if (a.n_jobs != (t.m[0] / 2 + 1) * (t.m[1] / 2 + 1) || 2 * a.R < t.m[0] - 1 || 2 * a.R < t.m[1] - 1)
         return hipErrorInvalidValue;
-    if (a.seg_rows <= 0 || a.seg_rows % 16 != 0 || 16 + 2 * a.R > 4 * Q || Q > kStreamMaxQuarter)
+    if (!stream_args_ok(a, Q))
         return hipErrorInvalidValue;
     const long long nb = (long long)a.n_xs * a.n_ys * a.n_jobs;
     if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidValue;
@@ -775,7 +795,7 @@ hipError_t launch_lsdft(int op, const StreamArgs& a, const LsdftTaps& t, int Q, 
 hipError_t launch_stream(int op, const StreamArgs& a, int Q, hipStream_t stream)
 {
     if (a.n_jobs <= 0) return hipSuccess;
-    if (a.seg_rows <= 0 || a.seg_rows % 16 != 0 || 16 + 2 * a.R > 4 * Q || Q > kStreamMaxQuarter)
+    if (!stream_args_ok(a, Q))
         return hipErrorInvalidValue;
     const long long nb = (long long)a.n_xs * a.n_ys * a.n_jobs;
     if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidValue;

@@ -101,10 +101,11 @@ extern "C" gabor_status lsdft_apply(const float* d_image, int32_t height, int32_
     const int op = fused_op_of(precision);
     if (op < 0) return GABOR_ERR_INVALID_ARG;
     // Limits of this build: tables in the launch arguments (M <= 64), 32-bit
-    // buffer offsets within the image and within each output plane.
+    // buffer offsets within the image and within each output plane (2^30
+    // bytes: 2^27 pixels).
     if (m_y > kLsdftMaxM || m_x > kLsdftMaxM) return GABOR_ERR_UNSUPPORTED;
     const int64_t npix = (int64_t)height * width;
-    if (npix >= (int64_t(1) << 29) || height > 65535) return GABOR_ERR_UNSUPPORTED;
+    if (npix > (int64_t(1) << 27) || height > 65535) return GABOR_ERR_UNSUPPORTED;
     if ((int64_t)(height - 1) * row_stride_elems + width >= (int64_t(1) << 30)) return GABOR_ERR_UNSUPPORTED;
 
     LsdftTaps t;

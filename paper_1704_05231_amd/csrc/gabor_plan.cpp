@@ -306,7 +306,7 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
         }
 
         // The fused kernel addresses the image and each output plane through
-        // 32-bit buffer offsets: planes of at most 2^29 pixels.
+        // 32-bit buffer offsets: planes of at most 2^27 pixels (2^30 bytes).
         int64_t f_row_macs = 0, f_col_macs = 0, f_outs = 0;
         for (const ColJob& jb : fjobs) {
             f_row_macs += (int64_t)(jb.j_real ? 1 : 2) * fd.K * npix;
@@ -314,7 +314,7 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
             f_outs += (jb.out_b >= 0 ? 2 : 1) * npix;
         }
         const int q = stream_quarter(p->fused_op, fd.R);
-        const bool fused = q <= kStreamMaxQuarter && algo != ALGO_TWOPASS && npix < (int64_t(1) << 29);
+        const bool fused = q <= kStreamMaxQuarter && algo != ALGO_TWOPASS && npix <= (int64_t(1) << 27);
         // Frequencies outside the fused kernel's range run the FP32 two-pass
         // kernels whatever the requested precision (never less accurate).
         FreqLaunch fl{};
@@ -858,7 +858,7 @@ extern "C" gabor_status gabor_bank_set_tuning(gabor_plan p, const int32_t* seg_r
 {
     if (!p || !seg_rows || n != p->O) return GABOR_ERR_INVALID_ARG;
     for (int i = 0; i < n; ++i)
-        if (p->launches[i].fused && (seg_rows[i] < 16 || seg_rows[i] % 16 != 0)) return GABOR_ERR_INVALID_ARG;
+        if (p->launches[i].fused && (seg_rows[i] < 32 || seg_rows[i] % 32 != 0)) return GABOR_ERR_INVALID_ARG;
     const int hmax = (p->H + 15) / 16 * 16;
     for (int i = 0; i < n; ++i)
         if (p->launches[i].fused) p->launches[i].seg_rows = std::min(seg_rows[i], hmax);

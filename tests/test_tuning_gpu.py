@@ -23,12 +23,12 @@ def test_autotune_keeps_results_bitwise(gpu_lib, prec):
     torch.cuda.synchronize()
     assert torch.equal(torch.view_as_real(before), torch.view_as_real(after))
     # a deliberately different schedule gives the same bits too
-    bank.tuning = [16] * len(tuned)
+    bank.tuning = [32] * len(tuned)
     again = bank(img)
     torch.cuda.synchronize()
     assert torch.equal(torch.view_as_real(before), torch.view_as_real(again))
     with pytest.raises(gpu_lib.GaborError):
-        bank.tuning = [24] * len(tuned)
+        bank.tuning = [48] * len(tuned)
     with pytest.raises(gpu_lib.GaborError):
         bank.tuning = [128] * (len(tuned) + 1)
     bank.close()
@@ -45,7 +45,7 @@ def test_tuning_cache_round_trip(gpu_lib, tmp_path):
     cache = tuning.load_cache(path)
     assert len(cache) == 1 and list(cache.values())[0] == seg
     bank2 = gpu_lib.GaborBank(200, 300, [1.0, 0.3], [2.0, 6.0], 4, None, 3.0, "zero", "fp16_split")
-    bank2.tuning = [16, 16]
+    bank2.tuning = [32, 32]
     assert tuning.tuned(bank2, img, path=path) == seg      # a cache hit: no retuning
     assert bank2.tuning == seg
     bank2.close()
