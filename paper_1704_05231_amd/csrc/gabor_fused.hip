@@ -4,7 +4,7 @@
 // and one 64-column strip of an image row segment.  It walks down the strip
 // 16 rows at a time:
 //   - the horizontal pass (Eq. (3), (5)-(6)) turns a 16-row image slab into
-//     16 new rows of J, kept in an LDS ring of the last L + 16 rows;
+//     16 new rows of J, kept in an LDS ring of the last L rows;
 //   - the vertical pass (Eq. (4), (7)-(10); Eq. (15)-(16) for the partner)
 //     reads the L-row window of J under the next 16 output rows and writes
 //     them to memory.
@@ -226,7 +226,7 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
     constexpr bool SPLIT = F::split;
     constexpr int NP = Q / F::PER;           // packs per fragment
     constexpr int L = 4 * Q;                 // contracted length per 16-block
-    constexpr int RING = L + 16;             // J rows held
+    constexpr int RING = L;                  // J rows held: one band window
     constexpr int PAD = 16 / sizeof(T);
     constexpr int RP = RING + PAD;           // J row pitch (per column)
     constexpr int WF = 48 + L;               // image slab columns
@@ -241,7 +241,7 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
 
     extern __shared__ float4 stream_lds4[];
     T* Jst = reinterpret_cast<T*>(stream_lds4);             // [NPL][2 comps][kSX][RP]
-    T* Fst = Jst + NPL * 2 * JPLANE;                         // [NPL][2 bufs][FROWS][WP]
+    T* Fst = Jst + NPL * 2 * JPLANE;                         // [NPL][FROWS][WP]
 
     const int xs = job_rest % a.n_xs, ys = job_rest / a.n_xs;
     const int x0 = xs * kSX, yseg = ys * a.seg_rows;
@@ -360,9 +360,9 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
             }
         }
     };
-    auto slab_store = [&](int b, const float (&pre)[2 * PER_T]) {
-        T* hi = Fst + (b & 1) * FBUF;
-        T* lo = hi + 2 * FBUF;
+    auto slab_store = [&](const float (&pre)[2 * PER_T]) {
+        T* hi = Fst;
+        T* lo = hi + FBUF;
 #pragma unroll
         for (int k = 0; k < PER_T; ++k) {
             W2 h, l;
@@ -381,10 +381,10 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
 
     // ---- horizontal pass of J block b (16 rows) for column block w
     auto row_pass = [&](int b) {
-        const T* fh = Fst + (b & 1) * FBUF + o * WP + 16 * w + Q * g;
+        const T* fh = Fst + o * WP + 16 * w + Q * g;
         Pack ah[NP], al[NP];
         frag_get(ah, fh);
-        if (SPLIT) frag_get(al, fh + 2 * FBUF);
+        if (SPLIT) frag_get(al, fh + FBUF);
         f4_t re = {0.f, 0.f, 0.f, 0.f}, im = re;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
@@ -489,48 +489,53 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
         }
     };
 
-    // Image slabs travel through two register sets that swap roles every
-    // step (no copies, which would wait for loads still in flight).
+    // Schedule.  Step b computes J block b (rows 16 b .. 16 b + 15 of the
+    // band) from the staged slab, then, once the whole workgroup has written
+    // it, output rows 16 s .. 16 s + 15 (s = b - LEAD + 1) from J blocks
+    // s .. b, then stages slab b + 1.  Two LDS barriers per step let one
+    // slab buffer and a ring of exactly one band window (L rows) serve:
+    // the first orders the J writes before the vertical reads and the slab
+    // reads before the next slab write; the second orders the vertical reads
+    // before the next step overwrites the oldest J block, and the slab write
+    // before its reads.  The smaller footprint keeps more workgroups
+    // resident per compute unit.  Image slabs travel through two register
+    // sets that swap roles every step (no copies, which would wait for loads
+    // still in flight); each is fetched two steps before it is staged.  The
+    // body has no branch: work past the segment end reads zeros or folded
+    // rows and its stores fall outside the output resources.
     constexpr int LEAD = L / 16;
     float pre_a[2 * PER_T], pre_b[2 * PER_T];
-
-    // ---- lead-in: J blocks 0 .. LEAD - 1.  Step b stages slab b (loaded
-    // one step earlier), fetches slab b + 1 and computes J block b.
     auto lead = [&](int b, float (&stg)[2 * PER_T], float (&fet)[2 * PER_T]) {
-        slab_load(b + 1, fet);
-        slab_store(b, stg);
-        lds_barrier();
+        slab_load(b + 2, fet);
         row_pass(b);
-    };
-    // ---- stream: step s computes J block s + LEAD (needed by step s + 1)
-    // and output rows 16 s .. 16 s + 15; it stages the slab of block
-    // s + LEAD + 1 (fetched one step earlier) and fetches the slab of block
-    // s + LEAD + 2, so every load has a whole step to land.  The body has no
-    // branch: work past the segment end reads zeros or folded rows and its
-    // stores fall outside the output resources.
-    auto step = [&](int s, float (&stg)[2 * PER_T], float (&fet)[2 * PER_T]) {
-        slab_load(s + LEAD + 2, fet);
-        row_pass(s + LEAD);
-        col_pass(s);
-        slab_store(s + LEAD + 1, stg);
+        lds_barrier();
+        slab_store(stg);
         lds_barrier();
     };
-
+    auto step = [&](int s, float (&stg)[2 * PER_T], float (&fet)[2 * PER_T]) {
+        const int b = s + LEAD - 1;
+        slab_load(b + 2, fet);
+        row_pass(b);
+        lds_barrier();
+        col_pass(s);
+        slab_store(stg);
+        lds_barrier();
+    };
     slab_load(0, pre_a);
-#pragma unroll
-    for (int b = 0; b < LEAD; b += 2) {
-        lead(b, pre_a, pre_b);
-        if (b + 1 < LEAD) lead(b + 1, pre_b, pre_a);
-    }
-    // The slab of block LEAD is in pre_a when LEAD is even, else in pre_b.
-    float (&s_lead)[2 * PER_T] = (LEAD % 2 == 0) ? pre_a : pre_b;
-    float (&s_next)[2 * PER_T] = (LEAD % 2 == 0) ? pre_b : pre_a;
-    slab_store(LEAD, s_lead);
-    slab_load(LEAD + 1, s_next);
+    slab_load(1, pre_b);
+    slab_store(pre_a);
     lds_barrier();
+    // lead-in: J blocks 0 .. LEAD - 2; slab k sits in pre_a for even k
+#pragma unroll
+    for (int b = 0; b < LEAD - 1; b += 2) {
+        lead(b, pre_b, pre_a);
+        if (b + 1 < LEAD - 1) lead(b + 1, pre_a, pre_b);
+    }
+    float (&m_stg)[2 * PER_T] = (LEAD % 2 == 0) ? pre_a : pre_b;
+    float (&m_fet)[2 * PER_T] = (LEAD % 2 == 0) ? pre_b : pre_a;
     for (int s = 0; s < nsteps; s += 2) {
-        step(s, s_next, s_lead);
-        step(s + 1, s_lead, s_next);
+        step(s, m_stg, m_fet);
+        step(s + 1, m_fet, m_stg);
     }
 }
 
@@ -762,13 +767,13 @@ int stream_quarter(int op, int R)
 
 size_t stream_lds_bytes(int op, int Q)
 {
-    const int L = 4 * Q, RING = L + 16, WF = 48 + L;
+    const int L = 4 * Q, RING = L, WF = 48 + L;
     const size_t es = op == FUSED_F32 ? 4 : 2;
     const int pad = (int)(16 / es);
     const size_t npl = (op == FUSED_BF16X3 || op == FUSED_F16X3) ? 2 : 1;
     const int per_t = (16 * WF / 2 + kThreads - 1) / kThreads;
     const int frows = (2 * per_t * kThreads + WF - 1) / WF;
-    return npl * es * (2 * (size_t)kSX * (RING + pad) + 2 * (size_t)frows * (WF + pad));
+    return npl * es * (2 * (size_t)kSX * (RING + pad) + (size_t)frows * (WF + pad));
 }
 
 int stream_strip_width() { return kSX; }
