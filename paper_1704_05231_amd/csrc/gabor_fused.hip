@@ -72,6 +72,7 @@ template <> struct Form<FUSED_F32> {
     static constexpr bool split = false;
     static constexpr bool drain = true;
     static constexpr bool scaled = false; // range scaling (float16 only)
+    static constexpr bool centred = false; // local offset removed before rounding
     // n consecutive floats -> packs (hi only)
     template <int N>
     static __device__ __forceinline__ void pack(const float (&x)[N], Pack* hi, Pack* lo)
@@ -119,6 +120,7 @@ template <typename E, bool SPLIT> struct Form16 {
     static constexpr bool split = SPLIT;
     static constexpr bool drain = false;
     static constexpr bool scaled = __is_same(E, _Float16);
+    static constexpr bool centred = !SPLIT;
     template <int N>
     static __device__ __forceinline__ void pack(const float (&x)[N], Pack* hi, Pack* lo)
     {
@@ -260,6 +262,9 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
     // Band fragments: lane (o, g) holds krev[Q g + e - o], e = 0..Q-1
     // (entry m of a table holds krev[m - 16]).
     Pack rch[NP], rcl[NP], rdh[NP], rdl[NP], cch[NP], ccl[NP], cdh[NP], cdl[NP];
+    // Single 16-bit forms: sums of the four tap sets (unscaled), for the
+    // response to a constant (see the local offset below).
+    float tsum[4] = {0.f, 0.f, 0.f, 0.f};
     {
         float x0v[Q], x1v[Q], x2v[Q], x3v[Q];
         if constexpr (LS) {
@@ -285,20 +290,45 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
 #pragma unroll
             for (int e = 0; e < Q; ++e) {
                 const int m = 16 + Q * g + e - o;
-                x0v[e] = sc(tl[m], rt_s);
-                x1v[e] = sc(tl[KT + m], rt_s);
-                x2v[e] = sc(tl[2 * KT + m], ct_s);
-                x3v[e] = sc(tl[3 * KT + m], ct_s);
+                x0v[e] = tl[m];
+                x1v[e] = tl[KT + m];
+                x2v[e] = tl[2 * KT + m];
+                x3v[e] = tl[3 * KT + m];
             }
         } else {
 #pragma unroll
             for (int e = 0; e < Q; ++e) {
                 const int m = 16 + Q * g + e - o;
-                x0v[e] = sc(tab[m], rt_s);
-                x1v[e] = sc(tab[KT + m], rt_s);
-                x2v[e] = sc(tab[2 * KT + m], ct_s);
-                x3v[e] = sc(tab[3 * KT + m], ct_s);
+                x0v[e] = tab[m];
+                x1v[e] = tab[KT + m];
+                x2v[e] = tab[2 * KT + m];
+                x3v[e] = tab[3 * KT + m];
             }
+        }
+        if constexpr (F::centred) {
+            // lanes o = 0 (one per lane group) hold krev[0 .. L-1] between
+            // them, which covers every nonzero tap
+#pragma unroll
+            for (int e = 0; e < Q; ++e) {
+                tsum[0] += x0v[e];
+                tsum[1] += x1v[e];
+                tsum[2] += x2v[e];
+                tsum[3] += x3v[e];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float v = o == 0 ? tsum[k] : 0.f;
+                v += __shfl_xor(v, 16);
+                v += __shfl_xor(v, 32);
+                tsum[k] = __shfl(v, 0);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < Q; ++e) {
+            x0v[e] = sc(x0v[e], rt_s);
+            x1v[e] = sc(x1v[e], rt_s);
+            x2v[e] = sc(x2v[e], ct_s);
+            x3v[e] = sc(x3v[e], ct_s);
         }
         F::template pack<Q>(x0v, rch, rcl);
         F::template pack<Q>(x1v, rdh, rdl);
@@ -337,8 +367,8 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
     // one reflection reaches every folded row when the band is shorter than
     // the image; otherwise the general (division) form
     const bool one_fold = 2 * R + 64 <= a.H;
-    auto slab_load = [&](int b, float (&pre)[2 * PER_T]) {
-        const int row0 = yseg - R + 16 * b;
+    // 16 image rows from row0 (folded or zero-extended by the boundary rule)
+    auto slab_rows = [&](int row0, float (&pre)[2 * PER_T]) {
         if (cols_inside && row0 >= 0 && row0 + 16 <= a.H) {
             // interior: no folding, one add per element
             const uint32_t base4 = (uint32_t)row0 * (uint32_t)a.stride * 4u;
@@ -360,13 +390,30 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
             }
         }
     };
+    auto slab_load = [&](int b, float (&pre)[2 * PER_T]) { slab_rows(yseg - R + 16 * b, pre); };
+    // Local offset (single 16-bit forms).  By linearity the bank of f equals
+    // the bank of f - c plus c times the response to a constant, and that
+    // response is (sum of the vertical taps) x (sum of the horizontal taps),
+    // conjugated on the horizontal factor for the pi - theta partner, at
+    // every pixel and for either boundary rule when c is subtracted from
+    // every sample the passes read (zero-extended ones included).  Each
+    // workgroup takes c as the mean of the 16 x (64 + L) slab of its strip
+    // at the middle rows of the image: J and the image are then rounded to
+    // 16 bits without their local mean, which removes the largest part of
+    // the rounding error of the low-frequency channels.  Every segment of a
+    // strip takes the same c, so results do not depend on the segment
+    // height.  The other forms use c = 0.
+    float cs = 0.f;
     auto slab_store = [&](const float (&pre)[2 * PER_T]) {
         T* hi = Fst;
         T* lo = hi + FBUF;
 #pragma unroll
         for (int k = 0; k < PER_T; ++k) {
             W2 h, l;
-            F::cvt2(sc(pre[2 * k], in_s), sc(pre[2 * k + 1], in_s), h, l);
+            if constexpr (F::centred)
+                F::cvt2(sc(pre[2 * k] - cs, in_s), sc(pre[2 * k + 1] - cs, in_s), h, l);
+            else
+                F::cvt2(sc(pre[2 * k], in_s), sc(pre[2 * k + 1], in_s), h, l);
             *reinterpret_cast<W2*>(hi + lds_at[k]) = h;
             if (SPLIT) *reinterpret_cast<W2*>(lo + lds_at[k]) = l;
         }
@@ -440,6 +487,9 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
     const uint32_t W8 = (uint32_t)a.W * 8u;
     const int xcol = x0 + 16 * w + o;
     const uint32_t lane_off = xcol < a.W ? ((uint32_t)(yseg + 4 * g) * (uint32_t)a.W + (uint32_t)xcol) * 8u : kFar;
+    // c times the constant responses (hc + i hd)(vc + i vd) and
+    // (hc - i hd)(vc + i vd); set once cs is known
+    float2 dc_a = make_float2(0.f, 0.f), dc_b = dc_a;
     auto col_pass = [&](int s) {
         Pack bah[NP], bal[NP], bbh[NP], bbl[NP];
         const T* base = Jst + (16 * w + o) * RP;
@@ -473,10 +523,17 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
             const float p1 = sc(P1[r], out_s), p2 = sc(P2[r], out_s);
             const float p3 = sc(P3[r], out_s), p4 = sc(P4[r], out_s);
             i2_t va, vb;
-            va[0] = __builtin_bit_cast(int, p1 - p2);
-            va[1] = __builtin_bit_cast(int, p3 + p4);
-            vb[0] = __builtin_bit_cast(int, p1 + p2);
-            vb[1] = __builtin_bit_cast(int, p3 - p4);
+            if constexpr (F::centred) {
+                va[0] = __builtin_bit_cast(int, (p1 - p2) + dc_a.x);
+                va[1] = __builtin_bit_cast(int, (p3 + p4) + dc_a.y);
+                vb[0] = __builtin_bit_cast(int, (p1 + p2) + dc_b.x);
+                vb[1] = __builtin_bit_cast(int, (p3 - p4) + dc_b.y);
+            } else {
+                va[0] = __builtin_bit_cast(int, p1 - p2);
+                va[1] = __builtin_bit_cast(int, p3 + p4);
+                vb[0] = __builtin_bit_cast(int, p1 + p2);
+                vb[1] = __builtin_bit_cast(int, p3 - p4);
+            }
             __builtin_amdgcn_raw_buffer_store_b64(va, out_a, (int)off, 0, 0);
             if constexpr (!JR) __builtin_amdgcn_raw_buffer_store_b64(vb, out_b, (int)off, 0, 0);
             if constexpr (LS) {
@@ -522,6 +579,29 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
         lds_barrier();
     };
     slab_load(0, pre_a);
+    if constexpr (F::centred) {
+        // mean of the strip's middle slab over the live lanes, summed in a
+        // fixed order
+        slab_rows(a.H > 16 ? a.H / 2 - 8 : 0, pre_b);
+        float v = 0.f;
+#pragma unroll
+        for (int k = 0; k < PER_T; ++k)
+            if (tid + k * kThreads < SLAB2) v += pre_b[2 * k] + pre_b[2 * k + 1];
+#pragma unroll
+        for (int sh = 32; sh >= 1; sh >>= 1) v += __shfl_xor(v, sh);
+        // past the localized-SDFT tap table at the start of the ring, which
+        // other waves may still be reading
+        float* red = reinterpret_cast<float*>(stream_lds4) + 4 * KT;
+        if (lane == 0) red[w] = v;
+        lds_barrier();
+        const float mean = ((red[0] + red[1]) + (red[2] + red[3])) * (1.0f / (16 * WF));
+        // rounded to 8 significant bits: any c is exact, and a constant
+        // image of such a value then cancels to zero before rounding
+        cs = __builtin_bit_cast(float, (__builtin_bit_cast(uint32_t, mean) + 0x8000u) & 0xFFFF0000u);
+        const float hc = tsum[0], hd = tsum[1], vc = tsum[2], vd = tsum[3];
+        dc_a = make_float2(cs * (vc * hc - vd * hd), cs * (vc * hd + vd * hc));
+        dc_b = make_float2(cs * (vc * hc + vd * hd), cs * (vd * hc - vc * hd));
+    }
     slab_load(1, pre_b);
     slab_store(pre_a);
     lds_barrier();

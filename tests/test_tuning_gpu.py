@@ -8,7 +8,7 @@ from paper_1704_05231_amd import workloads
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16_split"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16_split", "bf16", "fp16"])
 def test_autotune_keeps_results_bitwise(gpu_lib, prec):
     import torch
     wl = workloads.bank_1024()
