@@ -159,14 +159,18 @@ hipError_t launch_adjoint(const float2* d_G, int H, int W, const AdjJob* d_jobs,
 // plane of n rows (lines extended by T rows on both sides by the boundary
 // rule), with modulation by exp(-i w l) before and demodulation by
 // exp(i w l) after, twiddles (cos, sin)(w l) at tw[tw_off + l + T].
+// Chunks per line of the block-parallel recursion (one wave each).
+constexpr int kIirChunks = 16;
 struct IirJob {
     const void* in;            // float [n][in_stride] or float2 [n][in_stride]
     float2* scratch;           // [n + 2T][cols] forward results
     float2* out;               // [n][out_stride], or null: out_base plane out_plane
     int64_t in_stride, out_stride;
     int32_t in_complex, conj;  // input type; conjugate a complex input
-    int32_t n, cols, T, tw_off, out_plane, pad_;
+    int32_t n, cols, T, tw_off, out_plane;
+    int32_t lc;                // chunk length: ceil((n + 2T) / kIirChunks)
     float a[4];                // w[m] = a0 u[m] - a1 w[m-1] - a2 w[m-2] - a3 w[m-3]
+    double apow[9];            // A^lc, row-major, A = [[-a1, -a2, -a3], [1, 0, 0], [0, 1, 0]]
 };
 // Transpose, horizontal jobs (on the transposed image, into d_JT planes
 // [W][H]), transpose back into d_J planes [H][W], vertical jobs (into the

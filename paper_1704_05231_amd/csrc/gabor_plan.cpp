@@ -561,6 +561,23 @@ extern "C" gabor_status gabor_bank_plan_iir(gabor_plan* out, int32_t height, int
     }
     std::vector<IirJob> hj, vj;
     std::vector<float2> tw;
+    // Chunk length of a line of n + 2T samples and the state map across a
+    // whole chunk, A^lc, in FP64 (A is the companion matrix of the
+    // recursion acting on the state (w[m], w[m-1], w[m-2])).
+    auto set_chunks = [](IirJob& j, const double* a) {
+        const int ext = j.n + 2 * j.T;
+        j.lc = (ext + kIirChunks - 1) / kIirChunks;
+        double P[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+        const double A[9] = {-a[1], -a[2], -a[3], 1, 0, 0, 0, 1, 0};
+        for (int k = 0; k < j.lc; ++k) {
+            double Q[9];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c)
+                    Q[3 * r + c] = A[3 * r] * P[c] + A[3 * r + 1] * P[3 + c] + A[3 * r + 2] * P[6 + c];
+            for (int q = 0; q < 9; ++q) P[q] = Q[q];
+        }
+        for (int q = 0; q < 9; ++q) j.apow[q] = P[q];
+    };
     std::vector<int> h_of_v;                                  // horizontal job feeding each vertical job
     int64_t h_scr = 0, v_scr = 0;
     for (int i = 0; i < n_freq; ++i) {
@@ -592,6 +609,7 @@ extern "C" gabor_status gabor_bank_plan_iir(gabor_plan* out, int32_t height, int
             h.out_stride = height;
             h.tw_off = (int)tw.size();
             for (int c = 0; c < 4; ++c) h.a[c] = (float)a[c];
+            set_chunks(h, a);
             push_twiddles(tw, omega[i] * cs[n], width, T);
             h_scr += (int64_t)(width + 2 * T) * height;
             const int hidx = (int)hj.size();
@@ -610,6 +628,7 @@ extern "C" gabor_status gabor_bank_plan_iir(gabor_plan* out, int32_t height, int
                 v.tw_off = vtw;
                 v.out_plane = i * n_orient + (side ? partner : n);
                 for (int c = 0; c < 4; ++c) v.a[c] = (float)a[c];
+                set_chunks(v, a);
                 v_scr += (int64_t)(height + 2 * T) * width;
                 vj.push_back(v);
                 h_of_v.push_back(hidx);
