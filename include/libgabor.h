@@ -87,7 +87,7 @@ const char* gabor_status_string(gabor_status status);
  *   radius_sigmas  truncation of S in units of sigma (3.0 gives R = 3 sigma).
  *   boundary       rule for samples outside the image.
  *   precision      arithmetic of the Gaussian contractions.  Frequencies the
- *                  fused kernel cannot take (R > 56, or planes of more than
+ *                  fused kernel cannot take (R > 104, or planes of more than
  *                  2^27 pixels) run the FP32 two-pass kernels whatever the
  *                  precision.
  *   hip_stream     stream used to upload the plan's tables.
@@ -174,7 +174,7 @@ gabor_status gabor_bank_apply_adjoint(gabor_plan plan, const void* d_grad_out, f
  * gabor_batch_apply runs Algorithm 1 on every bound image: one persistent
  * launch per operand size of the fused kernel, each over the tiles of all
  * images, plus FP32 two-pass launches over all images for frequencies
- * outside the fused kernel's range (R > 56, or planes of more than 2^27
+ * outside the fused kernel's range (R > 104, or planes of more than 2^27
  * pixels; their intermediate planes live in a batch-owned workspace allocated
  * by gabor_batch_create).  It allocates and copies nothing, so it may be
  * captured in a HIP graph and replayed; the images are read and the outputs
@@ -243,16 +243,17 @@ gabor_status lsdft_work(int32_t height, int32_t width, int32_t m_y, int32_t m_x,
 /*
  * Autotuning (schedule only; results do not depend on it).  Each frequency
  * on the fused kernel streams strip segments of seg_rows image rows per
- * workgroup (a multiple of 16; each segment recomputes a lead-in of about 2R
- * rows of the horizontal pass).  gabor_bank_autotune times every candidate
+ * workgroup (a multiple of 32, or the whole image height; each segment
+ * recomputes a lead-in of about 2R rows of the horizontal pass).  gabor_bank_autotune times every candidate
  * segment height per fused frequency on the caller's image and output
  * buffers (d_out is overwritten) and keeps the fastest median of `reps`
  * timed launches; it then times whole applies with every height scaled by
  * 1, 2 and 4 (the frequencies run concurrently) and keeps the fastest.  It
  * synchronises hip_stream.  get/set copy the chosen heights
  * (n = number of frequencies; 0 for frequencies on the two-pass kernels) so
- * that a caller can cache them; set rejects heights that are not positive
- * multiples of 32.  Batches created afterwards use the new heights.
+ * that a caller can cache them; set rejects heights below the image height
+ * that are not positive multiples of 32, and clamps the others to the image
+ * height rounded up to 16.  Batches created afterwards use the new heights.
  */
 gabor_status gabor_bank_autotune(gabor_plan plan, const float* d_image, int64_t row_stride_elems,
                                  void* d_out, int32_t reps, void* hip_stream);

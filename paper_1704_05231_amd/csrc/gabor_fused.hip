@@ -72,7 +72,8 @@ template <> struct Form<FUSED_F32> {
     static constexpr bool split = false;
     static constexpr bool drain = true;
     static constexpr bool scaled = false; // range scaling (float16 only)
-    static constexpr bool centred = false; // local offset removed before rounding
+    static constexpr bool centred = true;    // local offset removed before accumulating
+    static constexpr int centre_from_q = 33; // only for quarters above 32 (R > 56)
     // n consecutive floats -> packs (hi only)
     template <int N>
     static __device__ __forceinline__ void pack(const float (&x)[N], Pack* hi, Pack* lo)
@@ -120,7 +121,8 @@ template <typename E, bool SPLIT> struct Form16 {
     static constexpr bool split = SPLIT;
     static constexpr bool drain = false;
     static constexpr bool scaled = __is_same(E, _Float16);
-    static constexpr bool centred = !SPLIT;
+    static constexpr bool centred = !SPLIT;  // local offset removed before rounding
+    static constexpr int centre_from_q = 0;
     template <int N>
     static __device__ __forceinline__ void pack(const float (&x)[N], Pack* hi, Pack* lo)
     {
@@ -240,6 +242,7 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
     constexpr int FROWS = (2 * PER_T * kThreads + WF - 1) / WF;
     constexpr int FBUF = FROWS * WP;         // one slab of one copy (+ padding rows)
     static_assert(16 % sizeof(T) == 0 && Q % (16 / sizeof(T)) == 0, "16-byte pieces");
+    constexpr bool CENTRE = F::centred && Q >= F::centre_from_q;   // local offset (below)
 
     extern __shared__ float4 stream_lds4[];
     T* Jst = reinterpret_cast<T*>(stream_lds4);             // [NPL][2 comps][kSX][RP]
@@ -262,8 +265,8 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
     // Band fragments: lane (o, g) holds krev[Q g + e - o], e = 0..Q-1
     // (entry m of a table holds krev[m - 16]).
     Pack rch[NP], rcl[NP], rdh[NP], rdl[NP], cch[NP], ccl[NP], cdh[NP], cdl[NP];
-    // Single 16-bit forms: sums of the four tap sets (unscaled), for the
-    // response to a constant (see the local offset below).
+    // Forms with the local offset: sums of the four tap sets (unscaled), for
+    // the response to a constant (see the local offset below).
     float tsum[4] = {0.f, 0.f, 0.f, 0.f};
     {
         float x0v[Q], x1v[Q], x2v[Q], x3v[Q];
@@ -305,7 +308,7 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
                 x3v[e] = tab[3 * KT + m];
             }
         }
-        if constexpr (F::centred) {
+        if constexpr (CENTRE) {
             // lanes o = 0 (one per lane group) hold krev[0 .. L-1] between
             // them, which covers every nonzero tap
 #pragma unroll
@@ -391,18 +394,21 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
         }
     };
     auto slab_load = [&](int b, float (&pre)[2 * PER_T]) { slab_rows(yseg - R + 16 * b, pre); };
-    // Local offset (single 16-bit forms).  By linearity the bank of f equals
-    // the bank of f - c plus c times the response to a constant, and that
-    // response is (sum of the vertical taps) x (sum of the horizontal taps),
+    // Local offset (single 16-bit forms; FP32 for R > 56).  By linearity
+    // the bank of f equals the bank of f - c plus c times the response to a
+    // constant, and that response is (sum of the vertical taps) x (sum of the horizontal taps),
     // conjugated on the horizontal factor for the pi - theta partner, at
     // every pixel and for either boundary rule when c is subtracted from
     // every sample the passes read (zero-extended ones included).  Each
     // workgroup takes c as the mean of the 16 x (64 + L) slab of its strip
     // at the middle rows of the image: J and the image are then rounded to
     // 16 bits without their local mean, which removes the largest part of
-    // the rounding error of the low-frequency channels.  Every segment of a
-    // strip takes the same c, so results do not depend on the segment
-    // height.  The other forms use c = 0.
+    // the rounding error of the low-frequency channels; in FP32 it keeps the
+    // accumulators and J near the size of the response, whose peak at
+    // omega sigma = pi is about 1 % of the image's mean (below R = 56 FP32
+    // meets its bar without it, and the extra registers cost about 4 %).
+    // Every segment of a strip takes the same c, so results do not depend on
+    // the segment height.  The split forms use c = 0.
     float cs = 0.f;
     auto slab_store = [&](const float (&pre)[2 * PER_T]) {
         T* hi = Fst;
@@ -410,7 +416,7 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
 #pragma unroll
         for (int k = 0; k < PER_T; ++k) {
             W2 h, l;
-            if constexpr (F::centred)
+            if constexpr (CENTRE)
                 F::cvt2(sc(pre[2 * k] - cs, in_s), sc(pre[2 * k + 1] - cs, in_s), h, l);
             else
                 F::cvt2(sc(pre[2 * k], in_s), sc(pre[2 * k + 1], in_s), h, l);
@@ -523,7 +529,7 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
             const float p1 = sc(P1[r], out_s), p2 = sc(P2[r], out_s);
             const float p3 = sc(P3[r], out_s), p4 = sc(P4[r], out_s);
             i2_t va, vb;
-            if constexpr (F::centred) {
+            if constexpr (CENTRE) {
                 va[0] = __builtin_bit_cast(int, (p1 - p2) + dc_a.x);
                 va[1] = __builtin_bit_cast(int, (p3 + p4) + dc_a.y);
                 vb[0] = __builtin_bit_cast(int, (p1 + p2) + dc_b.x);
@@ -579,14 +585,16 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
         lds_barrier();
     };
     slab_load(0, pre_a);
-    if constexpr (F::centred) {
+    slab_load(1, pre_b);
+    if constexpr (CENTRE) {
         // mean of the strip's middle slab over the live lanes, summed in a
-        // fixed order
-        slab_rows(a.H > 16 ? a.H / 2 - 8 : 0, pre_b);
+        // fixed order (its registers are free again once c is known)
+        float mid[2 * PER_T];
+        slab_rows(a.H > 16 ? a.H / 2 - 8 : 0, mid);
         float v = 0.f;
 #pragma unroll
         for (int k = 0; k < PER_T; ++k)
-            if (tid + k * kThreads < SLAB2) v += pre_b[2 * k] + pre_b[2 * k + 1];
+            if (tid + k * kThreads < SLAB2) v += mid[2 * k] + mid[2 * k + 1];
 #pragma unroll
         for (int sh = 32; sh >= 1; sh >>= 1) v += __shfl_xor(v, sh);
         // past the localized-SDFT tap table at the start of the ring, which
@@ -599,10 +607,14 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
         // image of such a value then cancels to zero before rounding
         cs = __builtin_bit_cast(float, (__builtin_bit_cast(uint32_t, mean) + 0x8000u) & 0xFFFF0000u);
         const float hc = tsum[0], hd = tsum[1], vc = tsum[2], vd = tsum[3];
-        dc_a = make_float2(cs * (vc * hc - vd * hd), cs * (vc * hd + vd * hc));
-        dc_b = make_float2(cs * (vc * hc + vd * hd), cs * (vd * hc - vc * hd));
+        // uniform over the workgroup: keep them in scalar registers
+        auto uni = [](float x) {
+            return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+        };
+        cs = uni(cs);
+        dc_a = make_float2(uni(cs * (vc * hc - vd * hd)), uni(cs * (vc * hd + vd * hc)));
+        dc_b = make_float2(uni(cs * (vc * hc + vd * hd)), uni(cs * (vd * hc - vc * hd)));
     }
-    slab_load(1, pre_b);
     slab_store(pre_a);
     lds_barrier();
     // lead-in: J blocks 0 .. LEAD - 2; slab k sits in pre_a for even k
@@ -768,8 +780,10 @@ hipError_t launch_lq(const StreamArgs& a, const LsdftTaps& t, int n_blocks, hipS
     return hipGetLastError();
 }
 
-// The quarters each form is built for: every R <= 56 for the bank, every
-// window M <= 64 (R <= 32) for the localized SDFT.
+// The quarters each form is built for: every R <= 104 for the bank, every
+// window M <= 64 (R <= 32) for the localized SDFT.  Quarters above 32 hold
+// their band fragments partly in the accumulation registers (one wave per
+// SIMD; their LDS footprint allows one workgroup per compute unit anyway).
 template <int OP, int... Qs>
 hipError_t launch_bank_q(const StreamArgs& a, int Q, int n_blocks, hipStream_t stream)
 {
@@ -799,9 +813,9 @@ template <>
 hipError_t stream_form<GABOR_FORM>(const StreamArgs& a, int Q, int n_blocks, hipStream_t stream)
 {
     if constexpr (GABOR_FORM == FUSED_F32)
-        return launch_bank_q<GABOR_FORM, 4, 8, 12, 16, 20, 24, 28, 32>(a, Q, n_blocks, stream);
+        return launch_bank_q<GABOR_FORM, 4, 8, 12, 16, 20, 24, 28, 32, 40, 48, 56>(a, Q, n_blocks, stream);
     else
-        return launch_bank_q<GABOR_FORM, 8, 16, 24, 32>(a, Q, n_blocks, stream);
+        return launch_bank_q<GABOR_FORM, 8, 16, 24, 32, 40, 48, 56>(a, Q, n_blocks, stream);
 }
 
 template <>
@@ -818,9 +832,9 @@ template <>
 hipError_t batch_form<GABOR_FORM>(const BatchArgs& b, int Q, hipStream_t stream)
 {
     if constexpr (GABOR_FORM == FUSED_F32)
-        return launch_batch_q<GABOR_FORM, 4, 8, 12, 16, 20, 24, 28, 32>(b, Q, stream);
+        return launch_batch_q<GABOR_FORM, 4, 8, 12, 16, 20, 24, 28, 32, 40, 48, 56>(b, Q, stream);
     else
-        return launch_batch_q<GABOR_FORM, 8, 16, 24, 32>(b, Q, stream);
+        return launch_batch_q<GABOR_FORM, 8, 16, 24, 32, 40, 48, 56>(b, Q, stream);
 }
 
 #if GABOR_FORM == 0
@@ -841,7 +855,7 @@ hipError_t launch_batch(int op, const BatchArgs& b, int Q, hipStream_t stream)
 int stream_quarter(int op, int R)
 {
     const int need = 16 + 2 * R;                         // inputs per 16-block
-    if (op == FUSED_F32) return ((need + 15) / 16) * 4;  // L multiple of 16
+    if (op == FUSED_F32 && need <= 128) return ((need + 15) / 16) * 4;  // L multiple of 16
     return ((need + 31) / 32) * 8;                       // L multiple of 32
 }
 

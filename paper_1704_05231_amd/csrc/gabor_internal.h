@@ -44,7 +44,7 @@ struct FreqDesc {
 // result and its vertical pass per workgroup over a 64-column strip, J held
 // in an LDS ring.
 enum FusedOp { FUSED_F32 = 0, FUSED_BF16 = 1, FUSED_BF16X3 = 2, FUSED_F16 = 3, FUSED_F16X3 = 4 };
-constexpr int kStreamMaxQuarter = 32;   // contracted length L = 4Q <= 128: R <= 56
+constexpr int kStreamMaxQuarter = 56;   // contracted length L = 4Q <= 224: R <= 104
 
 struct FusedJob {
     int32_t out_a;     // output plane of F = J * k

@@ -877,7 +877,8 @@ extern "C" gabor_status gabor_bank_set_tuning(gabor_plan p, const int32_t* seg_r
 {
     if (!p || !seg_rows || n != p->O) return GABOR_ERR_INVALID_ARG;
     for (int i = 0; i < n; ++i)
-        if (p->launches[i].fused && (seg_rows[i] < 32 || seg_rows[i] % 32 != 0)) return GABOR_ERR_INVALID_ARG;
+        if (p->launches[i].fused && seg_rows[i] < p->H && (seg_rows[i] < 32 || seg_rows[i] % 32 != 0))
+            return GABOR_ERR_INVALID_ARG;    // a segment that does not cover the image: multiple of 32 rows
     const int hmax = (p->H + 15) / 16 * 16;
     for (int i = 0; i < n; ++i)
         if (p->launches[i].fused) p->launches[i].seg_rows = std::min(seg_rows[i], hmax);

@@ -12,7 +12,8 @@ from paper_1704_05231_amd import workloads
 pytestmark = pytest.mark.gpu
 
 SIZES = [(37, 53), (64, 64), (1, 17), (100, 33), (9, 11), (70, 129), (23, 1), (128, 200)]
-# R = 6, 24 (fused) and 60 (beyond the fused kernel: two-pass FP32)
+# R = 6, 24 and 60, all in the fused kernel; "fp32_twopass" forces the
+# two-pass FP32 kernels (the path of R > 104) for every frequency
 OMEGAS = [math.pi / 2, math.pi / 8, math.pi / 40]
 SIGMAS = [2.0, 8.0, 20.0]
 N = 6
@@ -35,15 +36,21 @@ def make_batch(gpu_lib, prec, boundary, sizes, seed0=600):
     return bank, batch, host, views
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp16_split", "bf16_split", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "fp16_split", "bf16_split", "bf16", "fp32_twopass"])
 @pytest.mark.parametrize("boundary", ["mirror", "zero"])
-def test_batch_matches_single_image_and_oracle(gpu_lib, prec, boundary):
+def test_batch_matches_single_image_and_oracle(gpu_lib, prec, boundary, monkeypatch):
     import torch
+    twopass = prec == "fp32_twopass"
+    if twopass:
+        monkeypatch.setenv("LIBGABOR_ALGO", "twopass")
+        prec = "fp32"
     bank, batch, host, views = make_batch(gpu_lib, prec, boundary, SIZES)
     outs = [o.cpu().numpy() for o in batch()]
     torch.cuda.synchronize()
     n_launch, n_tiles = batch.info
-    assert n_launch >= 1 and n_tiles > 0
+    # persistent fused launches and their tiles (none when every frequency
+    # takes the two-pass kernels)
+    assert (n_launch, n_tiles) == (0, 0) if twopass else (n_launch >= 1 and n_tiles > 0)
     thetas = workloads.orientations(N)
     for i, (im, v) in enumerate(zip(host, views)):
         single = gpu_lib.GaborBank(im.shape[0], im.shape[1], OMEGAS, SIGMAS, N, None, 3.0, boundary, prec)
@@ -55,9 +62,6 @@ def test_batch_matches_single_image_and_oracle(gpu_lib, prec, boundary):
         den = np.abs(ref).reshape(len(OMEGAS), N, -1).max(-1)
         err = num / den
         tol = TOLS[prec] if prec in TOLS else 8 * UNIT[prec] * np.abs(im).max() / den
-        # the R = 60 frequency always runs in FP32
-        tol = np.broadcast_to(np.asarray(tol, dtype=float), err.shape).copy()
-        tol[2] = 1e-5
         assert np.all(err <= tol), f"image {i}: {err.max():.3e}"
     batch.close()
     bank.close()

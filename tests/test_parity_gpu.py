@@ -83,6 +83,8 @@ CASES = [
     (48, 40, [1.1], [2.2], 5, [0.0, 0.4, math.pi - 0.4, 1.0, math.pi / 2], "mirror"),  # unpaired 1.0
     (33, 65, [0.8], [1.7], 4, [math.pi / 2, 3 * math.pi / 2, -0.3, math.pi + 0.3], "zero"),
     (130, 300, [math.pi / 16], [16.0], 8, None, "mirror"),             # R = 48 over a ragged tile
+    (150, 170, [math.pi / 30, 0.2], [25.0, 12.0], 6, None, "mirror"),  # R = 75, 36
+    (90, 200, [math.pi / 32], [32.0], 4, None, "zero"),               # R = 96 > image height
 ]
 
 
