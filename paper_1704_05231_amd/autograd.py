@@ -28,6 +28,33 @@ class GaborBankFunction(torch.autograd.Function):
         return grad_img, None
 
 
+class GaborBatchFunction(torch.autograd.Function):
+    """F[b] = bank(f[b]) for a float32 [B, H, W] batch, every image written
+    straight into its slice of one complex64 [B, O, N, H, W] output; the
+    backward writes each image's dL/df into its slice of one [B, H, W]
+    gradient."""
+
+    @staticmethod
+    def forward(ctx, x, bank):
+        ctx.bank = bank
+        x = x.contiguous()
+        out = torch.empty((x.shape[0], bank.n_freq, bank.n_orient, bank.height, bank.width),
+                          dtype=torch.complex64, device=x.device)
+        for b in range(x.shape[0]):
+            bank(x[b], out[b])
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        grad_out = grad_out.contiguous()
+        bank = ctx.bank
+        grad = torch.empty((grad_out.shape[0], bank.height, bank.width), dtype=torch.float32,
+                           device=grad_out.device)
+        for b in range(grad_out.shape[0]):
+            bank.adjoint(grad_out[b], grad[b])
+        return grad, None
+
+
 class GaborLayer(torch.nn.Module):
     """Gabor bank over a batch of single-channel images.
 
@@ -48,7 +75,7 @@ class GaborLayer(torch.nn.Module):
             return GaborBankFunction.apply(x, self.bank)
         if x.dim() != 3:
             raise ValueError("expected [B, H, W] or [H, W]")
-        return torch.stack([GaborBankFunction.apply(x[b], self.bank) for b in range(x.shape[0])])
+        return GaborBatchFunction.apply(x, self.bank)
 
     def close(self):
         self.bank.close()
