@@ -371,13 +371,17 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
     // the image; otherwise the general (division) form
     const bool one_fold = 2 * R + 64 <= a.H;
     // 16 image rows from row0 (folded or zero-extended by the boundary rule)
+    // The two cases only form byte offsets; the loads are issued after the
+    // branch, so the outstanding-access count is the same on both paths and
+    // the compiler need not drain every load and store in flight (the
+    // previous step's output stores included) before reusing the registers.
     auto slab_rows = [&](int row0, float (&pre)[2 * PER_T]) {
+        uint32_t off[2 * PER_T];
         if (cols_inside && row0 >= 0 && row0 + 16 <= a.H) {
             // interior: no folding, one add per element
             const uint32_t base4 = (uint32_t)row0 * (uint32_t)a.stride * 4u;
 #pragma unroll
-            for (int k = 0; k < 2 * PER_T; ++k)
-                pre[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(img_rsrc, (int)(base4 + rel4[k]), 0, 0));
+            for (int k = 0; k < 2 * PER_T; ++k) off[k] = base4 + rel4[k];
         } else {
 #pragma unroll
             for (int k = 0; k < PER_T; ++k) {
@@ -387,17 +391,20 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int cx = col_of[2 * k + h];
-                    const uint32_t off = (yy >= 0 && cx >= 0) ? (rowoff + (uint32_t)cx) * 4u : kOutside;
-                    pre[2 * k + h] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(img_rsrc, (int)off, 0, 0));
+                    off[2 * k + h] = (yy >= 0 && cx >= 0) ? (rowoff + (uint32_t)cx) * 4u : kOutside;
                 }
             }
         }
+#pragma unroll
+        for (int k = 0; k < 2 * PER_T; ++k)
+            pre[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(img_rsrc, (int)off[k], 0, 0));
     };
     auto slab_load = [&](int b, float (&pre)[2 * PER_T]) { slab_rows(yseg - R + 16 * b, pre); };
     // Local offset (single 16-bit forms; FP32 for R > 56).  By linearity
     // the bank of f equals the bank of f - c plus c times the response to a
-    // constant, and that response is (sum of the vertical taps) x (sum of the horizontal taps),
-    // conjugated on the horizontal factor for the pi - theta partner, at
+    // constant, and that response is (sum of the vertical taps) x (sum of
+    // the horizontal taps), conjugated on the horizontal factor for the
+    // pi - theta partner, at
     // every pixel and for either boundary rule when c is subtracted from
     // every sample the passes read (zero-extended ones included).  Each
     // workgroup takes c as the mean of the 16 x (64 + L) slab of its strip
