@@ -274,14 +274,19 @@ def bench_layer(binding, workloads, steps, warmup):
     xs, ys = workloads.sample_pixels(H, W, 8, 55)
     ref = oracle.gabor_grad_points(wl.images[0], wl.omegas, wl.sigmas, wl.thetas_or_default, xs, ys) / B
     err = float(np.abs(g[0][ys, xs] - ref).max() / np.abs(ref).max())
-    adj = prof.get("adjoint_fp32")
+    # the matrix-core adjoint (fused frequencies) or the vector-ALU one
+    mfma = "adjoint_mfma_fp32" in prof
+    adj = prof.get("adjoint_mfma_fp32" if mfma else "adjoint_fp32")
     adj_roof = None
     if adj:
         avg = adj["total_ms"] / adj["launches"]
         tf = 2 * adj["real_macs"] / (avg * 1e-3) / 1e12
-        adj_roof = {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_TFLOPS["fp32_vector"],
-                    "unit": "TFLOP/s", "frac": round(tf / PEAK_TFLOPS["fp32_vector"], 4), "traffic": None,
-                    "launch_ms": round(avg, 5), "kernel": "adjoint_fp32 (row + column pass)"}
+        peak = PEAK_TFLOPS["fp32_mfma" if mfma else "fp32_vector"]
+        adj_roof = {"bound": "mfma" if mfma else "alu", "achieved": round(tf, 3), "peak": peak,
+                    "unit": "TFLOP/s", "frac": round(tf / peak, 4), "traffic": None,
+                    "launch_ms": round(avg, 5),
+                    "kernel": ("k_adj_stream, one launch per frequency" if mfma
+                               else "adjoint_fp32 (row + column pass)")}
     layer.close()
     n_out = B * len(wl.omegas) * wl.n_orient * H * W
     return {"workload": wl.name, "ms_forward_backward": round(ms, 4), "value": n_out / (ms * 1e-3),

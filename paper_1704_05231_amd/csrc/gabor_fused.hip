@@ -807,6 +807,276 @@ hipError_t launch_lsdft_q(const StreamArgs& a, const LsdftTaps& t, int Q, int n_
     return e;
 }
 
+
+// ---------------------------------------------------------------------------
+// Adjoint on the matrix cores.  For a real loss and G_c = dL/dRe F_c +
+// i dL/dIm F_c, dL/df = sum_c Re(G_c * K_c) with the same (Hermitian) Gabor
+// kernels as the forward bank.  For a pair theta, pi - theta with horizontal
+// taps h = c + i d (and conj(h) for the partner) and vertical taps v:
+//   J = h * G_a + conj(h) * G_b,
+//   J_re = c * (Ga_re + Gb_re) - d * (Ga_im - Gb_im),
+//   J_im = c * (Ga_im + Gb_im) + d * (Ga_re - Gb_re),
+//   dL/df += Re(v * J) = v_c * J_re - v_d * J_im,
+// which is the streaming kernel's structure with four staged real planes in
+// the horizontal pass and the forward's Re F_a in the vertical one.  A
+// workgroup owns one job and one 64-column strip segment and writes the
+// job's partial plane; a second kernel sums the planes in job order (no
+// atomics: the result is deterministic).
+template <int Q, bool HR, bool CR>
+__device__ __forceinline__ void adj_job(const AdjStreamArgs& a, const FusedJob& jb, int job, int x0, int yseg,
+                                        int nsteps)
+{
+    using F = Form<FUSED_F32>;
+    constexpr int L = 4 * Q;
+    constexpr int RING = L;
+    constexpr int PAD = 4;
+    constexpr int RP = RING + PAD;
+    constexpr int WF = 48 + L;
+    constexpr int WP = WF + PAD;
+    constexpr int JPLANE = kSX * RP;
+    constexpr int SLAB2 = 16 * WF / 2;
+    constexpr int PER_T = (SLAB2 + kThreads - 1) / kThreads;
+    constexpr int FROWS = (2 * PER_T * kThreads + WF - 1) / WF;
+    constexpr int FBUF = FROWS * WP;
+    constexpr int KT = L + 16;
+    constexpr int LEAD = L / 16;
+
+    extern __shared__ float4 stream_lds4[];
+    float* Jst = reinterpret_cast<float*>(stream_lds4);     // [2 comps][kSX][RP]
+    float* Fst = Jst + 2 * JPLANE;                           // [4 planes][FROWS][WP]
+
+    const int R = a.R;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int o = lane & 15, g = lane >> 4;
+    const float* tab = a.taps + jb.tap_off;
+
+    float rc[Q], rd[Q], cc[Q], cd[Q];
+#pragma unroll
+    for (int e = 0; e < Q; ++e) {
+        const int m = 16 + Q * g + e - o;
+        rc[e] = tab[m];
+        rd[e] = tab[KT + m];
+        cc[e] = tab[2 * KT + m];
+        cd[e] = tab[3 * KT + m];
+    }
+
+    // staged planes: S1 = Ga_re + Gb_re, N2 = Gb_im - Ga_im, S2 = Ga_im + Gb_im,
+    // D1 = Ga_re - Gb_re; samples outside the image are zero
+    const int64_t plane = (int64_t)a.H * a.W;
+    const uint32_t plane_bytes = (uint32_t)(plane * 8);
+    const __amdgpu_buffer_rsrc_t ga = make_rsrc(a.G + (int64_t)jb.out_a * plane, plane_bytes);
+    const __amdgpu_buffer_rsrc_t gb = jb.out_b >= 0 ? make_rsrc(a.G + (int64_t)jb.out_b * plane, plane_bytes)
+                                                    : make_rsrc(a.G, 0u);
+    int col_of[2 * PER_T], lds_at[PER_T], row_of[PER_T];
+    const int xs0 = x0 - R;
+#pragma unroll
+    for (int k = 0; k < PER_T; ++k) {
+        const int idx = tid + k * kThreads;
+        const int e = 2 * idx;
+        const int r = e / WF, c = e - r * WF;
+        const bool live = idx < SLAB2;
+        row_of[k] = r;
+        lds_at[k] = r * WP + c;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int cx = xs0 + c + h;
+            col_of[2 * k + h] = live && cx >= 0 && cx < a.W ? cx : -1;
+        }
+    }
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    auto slab_load = [&](int b, f2v (&pa)[2 * PER_T], f2v (&pb)[2 * PER_T]) {
+        const int row0 = yseg - R + 16 * b;
+        uint32_t off[2 * PER_T];
+#pragma unroll
+        for (int k = 0; k < PER_T; ++k) {
+            const int yy = row0 + row_of[k];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int cx = col_of[2 * k + h];
+                off[2 * k + h] = (yy >= 0 && yy < a.H && cx >= 0)
+                                     ? (uint32_t)(((int64_t)yy * a.W + cx) * 8) : kOutside;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 2 * PER_T; ++k) {
+            pa[k] = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(ga, (int)off[k], 0, 0));
+            pb[k] = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(gb, (int)off[k], 0, 0));
+        }
+    };
+    auto slab_store = [&](const f2v (&pa)[2 * PER_T], const f2v (&pb)[2 * PER_T]) {
+#pragma unroll
+        for (int k = 0; k < PER_T; ++k) {
+            const f2v a0 = pa[2 * k], a1 = pa[2 * k + 1], b0 = pb[2 * k], b1 = pb[2 * k + 1];
+            f2v s1, n2, s2, d1;
+            s1[0] = a0[0] + b0[0]; s1[1] = a1[0] + b1[0];
+            n2[0] = b0[1] - a0[1]; n2[1] = b1[1] - a1[1];
+            s2[0] = a0[1] + b0[1]; s2[1] = a1[1] + b1[1];
+            d1[0] = a0[0] - b0[0]; d1[1] = a1[0] - b1[0];
+            *reinterpret_cast<f2v*>(Fst + lds_at[k]) = s1;
+            *reinterpret_cast<f2v*>(Fst + FBUF + lds_at[k]) = n2;
+            *reinterpret_cast<f2v*>(Fst + 2 * FBUF + lds_at[k]) = s2;
+            *reinterpret_cast<f2v*>(Fst + 3 * FBUF + lds_at[k]) = d1;
+        }
+    };
+    auto frag = [&](float (&dst)[Q], const float* src) {
+#pragma unroll
+        for (int p = 0; p < Q; p += PAD)
+            *reinterpret_cast<float4*>(dst + p) = *reinterpret_cast<const float4*>(src + p);
+    };
+
+    // horizontal pass of J block b, column block w
+    auto row_pass = [&](int b) {
+        const float* fb = Fst + o * WP + 16 * w + Q * g;
+        float s1[Q], s2[Q];
+        frag(s1, fb);
+        frag(s2, fb + 2 * FBUF);
+        f4_t re = {0.f, 0.f, 0.f, 0.f}, im = re;
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+            F::mma1(re, s1[p], 0.f, rc[p], 0.f);
+            F::mma1(im, s2[p], 0.f, rc[p], 0.f);
+        }
+        if constexpr (!HR) {
+            float n2[Q], d1[Q];
+            frag(n2, fb + FBUF);
+            frag(d1, fb + 3 * FBUF);
+#pragma unroll
+            for (int p = 0; p < Q; ++p) {
+                F::mma1(re, n2[p], 0.f, rd[p], 0.f);
+                F::mma1(im, d1[p], 0.f, rd[p], 0.f);
+            }
+        }
+        f32_mfma_drain(re, im);
+        const int slot = (16 * b) % RING + 4 * g;
+        float* ja = Jst + (16 * w + o) * RP + slot;
+        *reinterpret_cast<float4*>(ja) = make_float4(re[0], re[1], re[2], re[3]);
+        *reinterpret_cast<float4*>(ja + JPLANE) = make_float4(im[0], im[1], im[2], im[3]);
+    };
+
+    // partial plane of the job; rows past the segment end are written only
+    // in the last step of an odd step count, which happens only where the
+    // segment reaches the image bottom, so the range check drops them
+    const uint32_t W4 = (uint32_t)a.W * 4u;
+    const __amdgpu_buffer_rsrc_t part = make_rsrc(a.part + (int64_t)job * plane, (uint32_t)(plane * 4));
+    const int xcol = x0 + 16 * w + o;
+    const uint32_t lane_off = xcol < a.W ? ((uint32_t)(yseg + 4 * g) * (uint32_t)a.W + (uint32_t)xcol) * 4u : kFar;
+
+    // vertical pass of output rows 16 s .. 16 s + 15
+    auto col_pass = [&](int s) {
+        float ba[Q], bb[Q];
+        const float* base = Jst + (16 * w + o) * RP;
+        int slot = (16 * s + Q * g) % RING;
+#pragma unroll
+        for (int p = 0; p < Q; p += PAD) {
+            *reinterpret_cast<float4*>(ba + p) = *reinterpret_cast<const float4*>(base + slot);
+            if constexpr (!CR)
+                *reinterpret_cast<float4*>(bb + p) = *reinterpret_cast<const float4*>(base + JPLANE + slot);
+            slot += PAD;
+            if (slot >= RING) slot -= RING;
+        }
+        f4_t P1 = {0.f, 0.f, 0.f, 0.f}, P2 = P1;
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+            F::mma1(P1, cc[p], 0.f, ba[p], 0.f);
+            if constexpr (!CR) F::mma1(P2, cd[p], 0.f, bb[p], 0.f);
+        }
+        f32_mfma_drain(P1, P2);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, P1[r] - P2[r]), part,
+                                                  (int)(lane_off + (uint32_t)(16 * s + r) * W4), 0, 0);
+    };
+
+    f2v xa[2 * PER_T], xb[2 * PER_T], ya[2 * PER_T], yb[2 * PER_T];
+    auto lead = [&](int b, f2v (&sa)[2 * PER_T], f2v (&sb)[2 * PER_T], f2v (&fa)[2 * PER_T],
+                    f2v (&fb)[2 * PER_T]) {
+        slab_load(b + 2, fa, fb);
+        row_pass(b);
+        lds_barrier();
+        slab_store(sa, sb);
+        lds_barrier();
+    };
+    auto step = [&](int s, f2v (&sa)[2 * PER_T], f2v (&sb)[2 * PER_T], f2v (&fa)[2 * PER_T],
+                    f2v (&fb)[2 * PER_T]) {
+        const int b = s + LEAD - 1;
+        slab_load(b + 2, fa, fb);
+        row_pass(b);
+        lds_barrier();
+        col_pass(s);
+        slab_store(sa, sb);
+        lds_barrier();
+    };
+    slab_load(0, xa, xb);
+    slab_load(1, ya, yb);
+    slab_store(xa, xb);
+    lds_barrier();
+    // slab k is in (xa, xb) for even k, (ya, yb) for odd k
+#pragma unroll
+    for (int b = 0; b < LEAD - 1; b += 2) {
+        lead(b, ya, yb, xa, xb);
+        if (b + 1 < LEAD - 1) lead(b + 1, xa, xb, ya, yb);
+    }
+    if constexpr (LEAD % 2 == 0) {
+        for (int s = 0; s < nsteps; s += 2) {
+            step(s, xa, xb, ya, yb);
+            step(s + 1, ya, yb, xa, xb);
+        }
+    } else {
+        for (int s = 0; s < nsteps; s += 2) {
+            step(s, ya, yb, xa, xb);
+            step(s + 1, xa, xb, ya, yb);
+        }
+    }
+}
+
+template <int Q>
+__global__ __launch_bounds__(kThreads) void k_adj_stream(AdjStreamArgs a)
+{
+    const int lid = xcd_local_id(blockIdx.x, gridDim.x);
+    const int job = lid % a.n_jobs, rest = lid / a.n_jobs;
+    const int xs = rest % a.n_xs, ys = rest / a.n_xs;
+    const int x0 = xs * kSX, yseg = ys * a.seg_rows;
+    const int nsteps = (min(a.seg_rows, a.H - yseg) + 15) / 16;
+    const FusedJob jb = a.jobs[job];
+    if (jb.j_real) adj_job<Q, true, false>(a, jb, job, x0, yseg, nsteps);
+    else if (jb.c_real) adj_job<Q, false, true>(a, jb, job, x0, yseg, nsteps);
+    else adj_job<Q, false, false>(a, jb, job, x0, yseg, nsteps);
+}
+
+__global__ __launch_bounds__(256) void k_adj_sum(const float* __restrict__ part, int n, int H, int W,
+                                                 float* __restrict__ grad, int64_t stride)
+{
+    const int64_t npix = (int64_t)H * W;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= npix) return;
+    float s = 0.f;
+    for (int j = 0; j < n; ++j) s += part[j * npix + i];
+    const int64_t y = i / W, x = i - y * W;
+    grad[y * stride + x] = s;
+}
+
+template <int Q>
+hipError_t launch_adj_q(const AdjStreamArgs& a, hipStream_t stream)
+{
+    const size_t lds = adjoint_stream_lds_bytes(Q);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_adj_stream<Q>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_adj_stream<Q>, dim3(a.n_jobs * a.n_xs * a.n_ys), dim3(kThreads), lds, stream, a);
+    return hipGetLastError();
+}
+
+template <int... Qs>
+hipError_t launch_adj_stream_q(const AdjStreamArgs& a, int Q, hipStream_t stream)
+{
+    hipError_t e = hipErrorInvalidValue;
+    ((Q == Qs ? (void)(e = launch_adj_q<Qs>(a, stream)) : (void)0), ...);
+    return e;
+}
+
 }  // namespace
 
 // One object per arithmetic form: this file is compiled once per value of
@@ -845,6 +1115,36 @@ hipError_t batch_form<GABOR_FORM>(const BatchArgs& b, int Q, hipStream_t stream)
 }
 
 #if GABOR_FORM == 0
+
+size_t adjoint_stream_lds_bytes(int Q)
+{
+    const int L = 4 * Q, WF = 48 + L;
+    const int per_t = (16 * WF / 2 + kThreads - 1) / kThreads;
+    const int frows = (2 * per_t * kThreads + WF - 1) / WF;
+    return 4 * ((size_t)2 * kSX * (L + 4) + (size_t)4 * frows * (WF + 4));
+}
+
+hipError_t launch_adjoint_stream(const AdjStreamArgs& a, int Q, hipStream_t stream)
+{
+    if (a.n_jobs <= 0) return hipSuccess;
+    if (!a.G || !a.part || !a.jobs || !a.taps || Q > kAdjStreamMaxQuarter || 16 + 2 * a.R > 4 * Q)
+        return hipErrorInvalidValue;
+    if (a.seg_rows <= 0 || a.seg_rows % 16 != 0 || (a.seg_rows % 32 != 0 && a.seg_rows < a.H)) return hipErrorInvalidValue;
+    if ((int64_t)a.H * a.W * 8 > (int64_t(1) << 30)) return hipErrorInvalidValue;
+    if ((long long)a.n_jobs * a.n_xs * a.n_ys > 0x7fffffffLL) return hipErrorInvalidValue;
+    return launch_adj_stream_q<4, 8, 12, 16, 20, 24, 28, 32>(a, Q, stream);
+}
+
+hipError_t launch_adjoint_sum(const float* part, int n, int H, int W, float* grad, int64_t grad_stride,
+                              hipStream_t stream)
+{
+    const int64_t npix = (int64_t)H * W;
+    if (n <= 0 || npix <= 0 || (npix + 255) / 256 > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_adj_sum, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, stream, part, n, H, W, grad,
+                       grad_stride);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch(int op, const BatchArgs& b, int Q, hipStream_t stream)
 {
     if (b.n_tiles <= 0) return hipSuccess;

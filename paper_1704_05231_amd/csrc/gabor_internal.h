@@ -72,6 +72,23 @@ struct StreamArgs {
     float tap_scale[2];        // horizontal, vertical tap scales
 };
 
+// Adjoint on the matrix cores: one launch per fused frequency (FP32), one
+// workgroup per (job, 64-column strip, row segment), each job writing its
+// own partial plane of dL/df; the planes are then summed in job order.
+struct AdjStreamArgs {
+    const float2* G;           // dL/dF planes [O N][H][W], complex64
+    float* part;               // partial planes of this frequency's jobs [n_jobs][H][W]
+    int32_t H, W, R, seg_rows, n_xs, n_ys, n_jobs, pad_;
+    const FusedJob* jobs;      // this frequency's jobs
+    const float* taps;         // reversed taps, fused-kernel layout [4][4Q + 16]
+};
+constexpr int kAdjStreamMaxQuarter = 32;   // R <= 56
+size_t adjoint_stream_lds_bytes(int Q);
+hipError_t launch_adjoint_stream(const AdjStreamArgs& a, int Q, hipStream_t stream);
+// dL/df[y][x] = sum over the n planes of part, in plane order
+hipError_t launch_adjoint_sum(const float* part, int n, int H, int W, float* grad, int64_t grad_stride,
+                              hipStream_t stream);
+
 // Batched bank (one persistent launch per operand quarter): images of any
 // size up to the plan's, each tile one (image, job, strip segment).
 struct BatchImage {

@@ -65,6 +65,7 @@ void release(gabor_plan p)
     if (p->d_fjobs) (void)hipFree(p->d_fjobs);
     if (p->d_J) (void)hipFree(p->d_J);
     if (p->d_ajobs) (void)hipFree(p->d_ajobs);
+    if (p->d_adjP) (void)hipFree(p->d_adjP);
     for (void* q : {(void*)p->d_ihj, (void*)p->d_ivj, (void*)p->d_itw, (void*)p->d_ifT, (void*)p->d_iJT,
                     (void*)p->d_iJ, (void*)p->d_iscr})
         if (q) (void)hipFree(q);
@@ -750,9 +751,62 @@ extern "C" gabor_status gabor_bank_apply_adjoint(gabor_plan p, const void* d_gra
     if (!p || !d_grad_out || !d_grad_image) return GABOR_ERR_INVALID_ARG;
     if (grad_row_stride_elems < p->W) return GABOR_ERR_INVALID_ARG;
     if (p->boundary != GABOR_BOUNDARY_ZERO || p->iir) return GABOR_ERR_UNSUPPORTED;
+    const int64_t npix = (int64_t)p->H * p->W;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    // On the matrix cores when every frequency runs in the fused kernel with
+    // a quarter of at most 32: one launch per frequency over its jobs, in
+    // stream order, the first writing dL/df and the others adding to it.
+    bool mfma = !p->launches.empty();
+    for (const FreqLaunch& fl : p->launches)
+        if (!fl.fused || fl.q > kAdjStreamMaxQuarter) mfma = false;
+    if (mfma) {
+        const int n_planes = (int)p->fjobs.size();
+        if (!p->d_adjP) {
+            const size_t bytes = (size_t)n_planes * (size_t)npix * sizeof(float);
+            if (env_flag("LIBGABOR_FAIL_ALLOC")) return GABOR_ERR_OUT_OF_MEMORY;
+            const hipError_t e = hipMalloc((void**)&p->d_adjP, bytes);
+            if (e != hipSuccess) {
+                p->d_adjP = nullptr;
+                return e == hipErrorOutOfMemory ? GABOR_ERR_OUT_OF_MEMORY : GABOR_ERR_DEVICE;
+            }
+            p->workspace_bytes += (int64_t)bytes;
+        }
+        LaunchTimer tm(p, stream, "adjoint_mfma_fp32", p->adj_row_macs + p->adj_col_macs,
+                       8 * (int64_t)p->O * p->N * npix + 4 * npix);
+        // the frequencies run concurrently as in the forward apply
+        const int n_aux = (int)p->aux.size();
+        if (n_aux > 0 && hipEventRecord(p->fork_ev[0], stream) != hipSuccess) return GABOR_ERR_DEVICE;
+        for (int k = 0; k < n_aux; ++k)
+            if (hipStreamWaitEvent(p->aux[k], p->fork_ev[0], 0) != hipSuccess) return GABOR_ERR_DEVICE;
+        for (size_t j = 0; j < p->order.size(); ++j) {
+            const int i = p->order[j];
+            const FreqLaunch& fl = p->launches[i];
+            hipStream_t ls = (j == 0 || n_aux == 0) ? stream : p->aux[(j - 1) % n_aux];
+            AdjStreamArgs a{};
+            a.G = (const float2*)d_grad_out;
+            a.part = p->d_adjP + (int64_t)fl.first * npix;
+            a.H = p->H;
+            a.W = p->W;
+            a.R = p->freqs[i].R;
+            a.seg_rows = fl.seg_rows;
+            a.n_xs = (p->W + stream_strip_width() - 1) / stream_strip_width();
+            a.n_ys = (p->H + fl.seg_rows - 1) / fl.seg_rows;
+            a.n_jobs = fl.count;
+            a.jobs = p->d_fjobs + fl.first;
+            a.taps = p->d_taps;
+            if (launch_adjoint_stream(a, fl.q, ls) != hipSuccess) return GABOR_ERR_DEVICE;
+        }
+        for (int k = 0; k < n_aux; ++k)
+            if (hipEventRecord(p->join_ev[k], p->aux[k]) != hipSuccess ||
+                hipStreamWaitEvent(stream, p->join_ev[k], 0) != hipSuccess)
+                return GABOR_ERR_DEVICE;
+        return launch_adjoint_sum(p->d_adjP, n_planes, p->H, p->W, d_grad_image, grad_row_stride_elems, stream) ==
+                       hipSuccess
+                   ? GABOR_OK
+                   : GABOR_ERR_DEVICE;
+    }
     if (adj_row_lds_bytes(p->adj_max_kp) > 160 * 1024 || adj_col_lds_bytes(p->adj_max_kp) > 160 * 1024)
         return GABOR_ERR_UNSUPPORTED;
-    const int64_t npix = (int64_t)p->H * p->W;
     if (!p->d_adjJ) {
         const size_t bytes = p->ajobs.size() * (size_t)npix * sizeof(float2);
         if (env_flag("LIBGABOR_FAIL_ALLOC")) return GABOR_ERR_OUT_OF_MEMORY;
@@ -763,7 +817,6 @@ extern "C" gabor_status gabor_bank_apply_adjoint(gabor_plan p, const void* d_gra
         }
         p->workspace_bytes += (int64_t)bytes;
     }
-    hipStream_t stream = (hipStream_t)hip_stream;
     LaunchTimer tm(p, stream, "adjoint_fp32", p->adj_row_macs + p->adj_col_macs,
                    8 * (int64_t)p->O * p->N * npix + 4 * npix);
     return launch_adjoint((const float2*)d_grad_out, p->H, p->W, p->d_ajobs, (int)p->ajobs.size(), p->adj_max_kp,

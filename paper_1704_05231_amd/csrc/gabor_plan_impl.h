@@ -43,6 +43,7 @@ struct gabor_plan_s {
     int64_t adj_row_macs = 0, adj_col_macs = 0;
     AdjJob* d_ajobs = nullptr;
     float2* d_adjJ = nullptr;              // adjoint workspace, allocated by the first adjoint call
+    float* d_adjP = nullptr;   // matrix-core adjoint: one partial plane per job (at first use)
     // recursive-smoother variant (gabor_bank_plan_iir)
     bool iir = false;
     int32_t n_ihj = 0, n_ivj = 0;

@@ -33,9 +33,14 @@ def make_bank(gpu_lib, H, W, om, sg, N, th):
     return gpu_lib.GaborBank(H, W, om, sg, N, th, 3.0, "zero", "fp32")
 
 
+# "fused": the matrix-core adjoint of fused plans; "twopass": plans on the
+# two-pass kernels take the vector-ALU adjoint
+@pytest.mark.parametrize("path", ["fused", "twopass"])
 @pytest.mark.parametrize("case", range(len(BANKS)))
-def test_adjoint_dot_product_identity(gpu_lib, case):
+def test_adjoint_dot_product_identity(gpu_lib, case, path, monkeypatch):
     import torch
+    if path == "twopass":
+        monkeypatch.setenv("LIBGABOR_ALGO", "twopass")
     H, W, om, sg, N, th = BANKS[case]
     bank = make_bank(gpu_lib, H, W, om, sg, N, th)
     rng = np.random.Generator(np.random.PCG64(500 + case))
@@ -47,7 +52,7 @@ def test_adjoint_dot_product_identity(gpu_lib, case):
     lhs = np.sum((np.conj(G.astype(np.complex128)) * F.astype(np.complex128)).real)
     rhs = np.sum(f.astype(np.float64) * g.astype(np.float64))
     scale = np.sum(np.abs(G) * np.abs(F))
-    print(f"adjoint case {case}: <Ff,G> = {lhs:.9e}, <f,A G> = {rhs:.9e}, rel {abs(lhs - rhs) / scale:.2e}")
+    print(f"adjoint case {case} {path}: <Ff,G> = {lhs:.9e}, <f,A G> = {rhs:.9e}, rel {abs(lhs - rhs) / scale:.2e}")
     assert abs(lhs - rhs) <= 1e-6 * scale
 
 
