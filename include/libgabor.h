@@ -149,10 +149,16 @@ gabor_status gabor_bank_apply(gabor_plan plan, const float* d_image,
  *                     i.e. sum_c Re((G_c * K_c)(q)): the Gabor kernel is
  *                     Hermitian, so the adjoint is the same bank applied to
  *                     the complex gradients, real part summed over channels.
+ *                     Under the mirror rule the sum runs over every position
+ *                     p - t whose fold is q (the transpose of the fold).
  *
- * Only plans with GABOR_BOUNDARY_ZERO are supported (a mirror plan returns
- * GABOR_ERR_UNSUPPORTED).  The arithmetic is FP32 whatever the plan's
- * precision.  The first call on a plan allocates its adjoint workspace (one
+ * Plans whose frequencies all run in the fused kernel with R <= 56 use the
+ * matrix cores (one partial plane per job, summed in job order); other zero
+ * boundary plans use the vector-ALU kernels.  Mirror plans need the former
+ * (and at most 32 frequencies), else GABOR_ERR_UNSUPPORTED.  The arithmetic
+ * is FP32 whatever the plan's precision, and the result is deterministic.
+ * The first call on a plan allocates its adjoint workspace (the partial
+ * planes, of (H + 2R) x (W + 2R) pixels under the mirror rule; or one
  * complex plane per horizontal pass), which the plan keeps until destroyed;
  * later calls allocate nothing.
  */

@@ -861,7 +861,8 @@ __device__ __forceinline__ void adj_job(const AdjStreamArgs& a, const FusedJob& 
     }
 
     // staged planes: S1 = Ga_re + Gb_re, N2 = Gb_im - Ga_im, S2 = Ga_im + Gb_im,
-    // D1 = Ga_re - Gb_re; samples outside the image are zero
+    // D1 = Ga_re - Gb_re; samples outside the image are zero.  Slab positions
+    // are output-grid coordinates; the image sits at offset a.off.
     const int64_t plane = (int64_t)a.H * a.W;
     const uint32_t plane_bytes = (uint32_t)(plane * 8);
     const __amdgpu_buffer_rsrc_t ga = make_rsrc(a.G + (int64_t)jb.out_a * plane, plane_bytes);
@@ -879,13 +880,13 @@ __device__ __forceinline__ void adj_job(const AdjStreamArgs& a, const FusedJob& 
         lds_at[k] = r * WP + c;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int cx = xs0 + c + h;
+            const int cx = xs0 + c + h - a.off;
             col_of[2 * k + h] = live && cx >= 0 && cx < a.W ? cx : -1;
         }
     }
     typedef float f2v __attribute__((ext_vector_type(2)));
     auto slab_load = [&](int b, f2v (&pa)[2 * PER_T], f2v (&pb)[2 * PER_T]) {
-        const int row0 = yseg - R + 16 * b;
+        const int row0 = yseg - R + 16 * b - a.off;
         uint32_t off[2 * PER_T];
 #pragma unroll
         for (int k = 0; k < PER_T; ++k) {
@@ -956,10 +957,11 @@ __device__ __forceinline__ void adj_job(const AdjStreamArgs& a, const FusedJob& 
     // partial plane of the job; rows past the segment end are written only
     // in the last step of an odd step count, which happens only where the
     // segment reaches the image bottom, so the range check drops them
-    const uint32_t W4 = (uint32_t)a.W * 4u;
-    const __amdgpu_buffer_rsrc_t part = make_rsrc(a.part + (int64_t)job * plane, (uint32_t)(plane * 4));
+    const int64_t plane_o = (int64_t)a.Ho * a.Wo;
+    const uint32_t W4 = (uint32_t)a.Wo * 4u;
+    const __amdgpu_buffer_rsrc_t part = make_rsrc(a.part + (int64_t)job * plane_o, (uint32_t)(plane_o * 4));
     const int xcol = x0 + 16 * w + o;
-    const uint32_t lane_off = xcol < a.W ? ((uint32_t)(yseg + 4 * g) * (uint32_t)a.W + (uint32_t)xcol) * 4u : kFar;
+    const uint32_t lane_off = xcol < a.Wo ? ((uint32_t)(yseg + 4 * g) * (uint32_t)a.Wo + (uint32_t)xcol) * 4u : kFar;
 
     // vertical pass of output rows 16 s .. 16 s + 15
     auto col_pass = [&](int s) {
@@ -1036,7 +1038,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_stream(AdjStreamArgs a)
     const int job = lid % a.n_jobs, rest = lid / a.n_jobs;
     const int xs = rest % a.n_xs, ys = rest / a.n_xs;
     const int x0 = xs * kSX, yseg = ys * a.seg_rows;
-    const int nsteps = (min(a.seg_rows, a.H - yseg) + 15) / 16;
+    const int nsteps = (min(a.seg_rows, a.Ho - yseg) + 15) / 16;
     const FusedJob jb = a.jobs[job];
     if (jb.j_real) adj_job<Q, true, false>(a, jb, job, x0, yseg, nsteps);
     else if (jb.c_real) adj_job<Q, false, true>(a, jb, job, x0, yseg, nsteps);
@@ -1053,6 +1055,61 @@ __global__ __launch_bounds__(256) void k_adj_sum(const float* __restrict__ part,
     for (int j = 0; j < n; ++j) s += part[j * npix + i];
     const int64_t y = i / W, x = i - y * W;
     grad[y * stride + x] = s;
+}
+
+// Mirror rule: dL/df(q) adds, for every frequency, the extended-grid values
+// at all positions u in [-R, n - 1 + R] (per axis) whose fold is q: the
+// residues of q and of -q modulo 2(n - 1) (one class when q is 0 or n - 1;
+// every u when n = 1).  Fixed order: frequency, row preimage, column
+// preimage, job.
+__device__ __forceinline__ int fold_first(int u0, int R, int p)
+{
+    // smallest u = u0 + k p with u >= -R
+    int k = (u0 + R) / p;
+    return u0 - k * p;
+}
+
+__global__ __launch_bounds__(256) void k_adj_fold_sum(AdjFoldArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)a.H * a.W) return;
+    const int qy = (int)(i / a.W), qx = (int)(i - (int64_t)qy * a.W);
+    float s = 0.f;
+    for (int f = 0; f < a.n_freq; ++f) {
+        const int R = a.f[f].R, Wo = a.W + 2 * R;
+        const int64_t plane = (int64_t)(a.H + 2 * R) * Wo;
+        const float* base = a.part + a.f[f].base;
+        for (int cy = 0; cy < 2; ++cy) {
+            int uy, py;
+            if (a.H == 1) {
+                if (cy) break;
+                uy = -R;
+                py = 1;
+            } else {
+                py = 2 * (a.H - 1);
+                if (cy && (qy == 0 || qy == a.H - 1)) break;
+                uy = fold_first(cy ? py - qy : qy, R, py);
+            }
+            for (; uy <= a.H - 1 + R; uy += py)
+                for (int cx = 0; cx < 2; ++cx) {
+                    int ux, px;
+                    if (a.W == 1) {
+                        if (cx) break;
+                        ux = -R;
+                        px = 1;
+                    } else {
+                        px = 2 * (a.W - 1);
+                        if (cx && (qx == 0 || qx == a.W - 1)) break;
+                        ux = fold_first(cx ? px - qx : qx, R, px);
+                    }
+                    for (; ux <= a.W - 1 + R; ux += px) {
+                        const int64_t e = (int64_t)(uy + R) * Wo + (ux + R);
+                        for (int j = 0; j < a.f[f].count; ++j) s += base[j * plane + e];
+                    }
+                }
+        }
+    }
+    a.grad[(int64_t)qy * a.grad_stride + qx] = s;
 }
 
 template <int Q>
@@ -1130,9 +1187,21 @@ hipError_t launch_adjoint_stream(const AdjStreamArgs& a, int Q, hipStream_t stre
     if (!a.G || !a.part || !a.jobs || !a.taps || Q > kAdjStreamMaxQuarter || 16 + 2 * a.R > 4 * Q)
         return hipErrorInvalidValue;
     if (a.seg_rows <= 0 || a.seg_rows % 16 != 0 || (a.seg_rows % 32 != 0 && a.seg_rows < a.H)) return hipErrorInvalidValue;
-    if ((int64_t)a.H * a.W * 8 > (int64_t(1) << 30)) return hipErrorInvalidValue;
+    if ((int64_t)a.H * a.W * 8 > (int64_t(1) << 30) || (int64_t)a.Ho * a.Wo * 4 > (int64_t(1) << 30))
+        return hipErrorInvalidValue;
+    if (a.Ho < a.H || a.Wo < a.W || a.off < 0 || a.n_xs * kSX < a.Wo || (int64_t)a.n_ys * a.seg_rows < a.Ho)
+        return hipErrorInvalidValue;
     if ((long long)a.n_jobs * a.n_xs * a.n_ys > 0x7fffffffLL) return hipErrorInvalidValue;
     return launch_adj_stream_q<4, 8, 12, 16, 20, 24, 28, 32>(a, Q, stream);
+}
+
+hipError_t launch_adjoint_fold_sum(const AdjFoldArgs& a, hipStream_t stream)
+{
+    const int64_t npix = (int64_t)a.H * a.W;
+    if (a.n_freq <= 0 || a.n_freq > kAdjFoldMaxFreq || npix <= 0 || (npix + 255) / 256 > 0x7fffffffLL)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_adj_fold_sum, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, stream, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_adjoint_sum(const float* part, int n, int H, int W, float* grad, int64_t grad_stride,

@@ -74,20 +74,40 @@ struct StreamArgs {
 
 // Adjoint on the matrix cores: one launch per fused frequency (FP32), one
 // workgroup per (job, 64-column strip, row segment), each job writing its
-// own partial plane of dL/df; the planes are then summed in job order.
+// own partial plane; the planes are then summed in job order.  The partial
+// planes cover an output grid Ho x Wo whose pixel (y, x) is image position
+// (y - off, x - off): the image itself for the zero boundary, the image
+// extended by R on every side for the mirror rule, whose sum then adds each
+// extended position into the pixel it folds to.
 struct AdjStreamArgs {
     const float2* G;           // dL/dF planes [O N][H][W], complex64
-    float* part;               // partial planes of this frequency's jobs [n_jobs][H][W]
-    int32_t H, W, R, seg_rows, n_xs, n_ys, n_jobs, pad_;
+    float* part;               // partial planes of this frequency's jobs [n_jobs][Ho][Wo]
+    int32_t H, W;              // image
+    int32_t Ho, Wo, off;       // output grid of the partial planes
+    int32_t R, seg_rows, n_xs, n_ys, n_jobs;
     const FusedJob* jobs;      // this frequency's jobs
     const float* taps;         // reversed taps, fused-kernel layout [4][4Q + 16]
 };
 constexpr int kAdjStreamMaxQuarter = 32;   // R <= 56
 size_t adjoint_stream_lds_bytes(int Q);
 hipError_t launch_adjoint_stream(const AdjStreamArgs& a, int Q, hipStream_t stream);
-// dL/df[y][x] = sum over the n planes of part, in plane order
+// zero boundary: dL/df[y][x] = sum over the n planes [H][W] of part, in plane order
 hipError_t launch_adjoint_sum(const float* part, int n, int H, int W, float* grad, int64_t grad_stride,
                               hipStream_t stream);
+// mirror rule: per frequency, planes [count][H + 2R][W + 2R] from element base
+struct AdjFoldFreq {
+    int64_t base;
+    int32_t R, count;
+};
+constexpr int kAdjFoldMaxFreq = 32;
+struct AdjFoldArgs {
+    const float* part;
+    float* grad;
+    int64_t grad_stride;
+    int32_t H, W, n_freq, pad_;
+    AdjFoldFreq f[kAdjFoldMaxFreq];
+};
+hipError_t launch_adjoint_fold_sum(const AdjFoldArgs& a, hipStream_t stream);
 
 // Batched bank (one persistent launch per operand quarter): images of any
 // size up to the plan's, each tile one (image, job, strip segment).

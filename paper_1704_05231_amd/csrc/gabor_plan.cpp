@@ -750,19 +750,30 @@ extern "C" gabor_status gabor_bank_apply_adjoint(gabor_plan p, const void* d_gra
 {
     if (!p || !d_grad_out || !d_grad_image) return GABOR_ERR_INVALID_ARG;
     if (grad_row_stride_elems < p->W) return GABOR_ERR_INVALID_ARG;
-    if (p->boundary != GABOR_BOUNDARY_ZERO || p->iir) return GABOR_ERR_UNSUPPORTED;
+    if (p->iir) return GABOR_ERR_UNSUPPORTED;
+    const bool mirror = p->boundary == GABOR_BOUNDARY_MIRROR;
     const int64_t npix = (int64_t)p->H * p->W;
     hipStream_t stream = (hipStream_t)hip_stream;
     // On the matrix cores when every frequency runs in the fused kernel with
     // a quarter of at most 32: one launch per frequency over its jobs, in
     // stream order, the first writing dL/df and the others adding to it.
-    bool mfma = !p->launches.empty();
+    // The mirror rule needs it: the sum then folds the extended grid.
+    bool mfma = !p->launches.empty() && (!mirror || p->O <= kAdjFoldMaxFreq);
     for (const FreqLaunch& fl : p->launches)
         if (!fl.fused || fl.q > kAdjStreamMaxQuarter) mfma = false;
+    if (mirror && !mfma) return GABOR_ERR_UNSUPPORTED;
     if (mfma) {
         const int n_planes = (int)p->fjobs.size();
+        // partial planes: [job][H][W], or [job][H + 2R][W + 2R] for the mirror rule
+        std::vector<int64_t> base(p->O);
+        int64_t total = 0;
+        for (int i = 0; i < p->O; ++i) {
+            const int R = mirror ? p->freqs[i].R : 0;
+            base[i] = total;
+            total += (int64_t)p->launches[i].count * (p->H + 2 * R) * (p->W + 2 * R);
+        }
         if (!p->d_adjP) {
-            const size_t bytes = (size_t)n_planes * (size_t)npix * sizeof(float);
+            const size_t bytes = (size_t)total * sizeof(float);
             if (env_flag("LIBGABOR_FAIL_ALLOC")) return GABOR_ERR_OUT_OF_MEMORY;
             const hipError_t e = hipMalloc((void**)&p->d_adjP, bytes);
             if (e != hipSuccess) {
@@ -784,13 +795,19 @@ extern "C" gabor_status gabor_bank_apply_adjoint(gabor_plan p, const void* d_gra
             hipStream_t ls = (j == 0 || n_aux == 0) ? stream : p->aux[(j - 1) % n_aux];
             AdjStreamArgs a{};
             a.G = (const float2*)d_grad_out;
-            a.part = p->d_adjP + (int64_t)fl.first * npix;
+            a.part = p->d_adjP + base[i];
             a.H = p->H;
             a.W = p->W;
             a.R = p->freqs[i].R;
-            a.seg_rows = fl.seg_rows;
-            a.n_xs = (p->W + stream_strip_width() - 1) / stream_strip_width();
-            a.n_ys = (p->H + fl.seg_rows - 1) / fl.seg_rows;
+            a.off = mirror ? a.R : 0;
+            a.Ho = p->H + 2 * a.off;
+            a.Wo = p->W + 2 * a.off;
+            // segments of a multiple of 32 rows unless one covers the grid
+            int seg = fl.seg_rows;
+            if (seg % 32 != 0 && seg < a.Ho) seg = (seg + 31) / 32 * 32;
+            a.seg_rows = seg;
+            a.n_xs = (a.Wo + stream_strip_width() - 1) / stream_strip_width();
+            a.n_ys = (a.Ho + seg - 1) / seg;
             a.n_jobs = fl.count;
             a.jobs = p->d_fjobs + fl.first;
             a.taps = p->d_taps;
@@ -800,6 +817,17 @@ extern "C" gabor_status gabor_bank_apply_adjoint(gabor_plan p, const void* d_gra
             if (hipEventRecord(p->join_ev[k], p->aux[k]) != hipSuccess ||
                 hipStreamWaitEvent(stream, p->join_ev[k], 0) != hipSuccess)
                 return GABOR_ERR_DEVICE;
+        if (mirror) {
+            AdjFoldArgs fa{};
+            fa.part = p->d_adjP;
+            fa.grad = d_grad_image;
+            fa.grad_stride = grad_row_stride_elems;
+            fa.H = p->H;
+            fa.W = p->W;
+            fa.n_freq = p->O;
+            for (int i = 0; i < p->O; ++i) fa.f[i] = AdjFoldFreq{base[i], p->freqs[i].R, p->launches[i].count};
+            return launch_adjoint_fold_sum(fa, stream) == hipSuccess ? GABOR_OK : GABOR_ERR_DEVICE;
+        }
         return launch_adjoint_sum(p->d_adjP, n_planes, p->H, p->W, d_grad_image, grad_row_stride_elems, stream) ==
                        hipSuccess
                    ? GABOR_OK

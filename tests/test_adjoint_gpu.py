@@ -1,8 +1,10 @@
 """GPU checks of the hand-written adjoint (gabor_bank_apply_adjoint) and the
-autograd layer built on it (zero boundary, FP32).
+autograd layer built on it (FP32).
 
 1. Dot-product identity: <bank(f), G> = <f, adjoint(G)> for random f and G,
-   with <F, G> = sum Re(conj(G) F), both sides summed in FP64.
+   with <F, G> = sum Re(conj(G) F), both sides summed in FP64; zero boundary
+   on both adjoint paths, and the mirror rule (the transpose of the fold) on
+   the matrix-core one, including images smaller than the band.
 2. The oracle's FP64 gradient of L = mean |F|^2 at sampled pixels.
 3. Central finite differences of the same loss (h = 1e-3) at sampled pixels,
    each difference formed as an FP64 sum over the outputs within R of the
@@ -26,23 +28,27 @@ BANKS = [
     (48, 40, [1.1], [2.2], 5, [0.0, 0.4, math.pi - 0.4, 1.0, math.pi / 2]),
     (20, 90, [0.0, 2.0], [3.0, 1.0], 3, None),                       # omega = 0
     (130, 70, [math.pi / 16], [16.0], 8, None),                      # R = 48 > half the width
+    (9, 11, [0.9], [4.0], 5, None),                                  # R = 12 > both sides
+    (1, 17, [1.0], [1.5], 3, None),                                  # one row
+    (23, 1, [1.0, 0.3], [1.5, 2.0], 4, None),                        # one column
 ]
 
 
-def make_bank(gpu_lib, H, W, om, sg, N, th):
-    return gpu_lib.GaborBank(H, W, om, sg, N, th, 3.0, "zero", "fp32")
+def make_bank(gpu_lib, H, W, om, sg, N, th, boundary="zero"):
+    return gpu_lib.GaborBank(H, W, om, sg, N, th, 3.0, boundary, "fp32")
 
 
-# "fused": the matrix-core adjoint of fused plans; "twopass": plans on the
-# two-pass kernels take the vector-ALU adjoint
-@pytest.mark.parametrize("path", ["fused", "twopass"])
+# "fused": the matrix-core adjoint of fused plans (both boundary rules; for
+# the mirror rule the transpose of the fold); "twopass": plans on the
+# two-pass kernels take the vector-ALU adjoint (zero boundary)
+@pytest.mark.parametrize("path,boundary", [("fused", "zero"), ("fused", "mirror"), ("twopass", "zero")])
 @pytest.mark.parametrize("case", range(len(BANKS)))
-def test_adjoint_dot_product_identity(gpu_lib, case, path, monkeypatch):
+def test_adjoint_dot_product_identity(gpu_lib, case, path, boundary, monkeypatch):
     import torch
     if path == "twopass":
         monkeypatch.setenv("LIBGABOR_ALGO", "twopass")
     H, W, om, sg, N, th = BANKS[case]
-    bank = make_bank(gpu_lib, H, W, om, sg, N, th)
+    bank = make_bank(gpu_lib, H, W, om, sg, N, th, boundary)
     rng = np.random.Generator(np.random.PCG64(500 + case))
     f = rng.uniform(-1, 1, (H, W)).astype(np.float32)
     G = (rng.uniform(-1, 1, (len(om), N, H, W)) + 1j * rng.uniform(-1, 1, (len(om), N, H, W))).astype(np.complex64)
@@ -52,7 +58,8 @@ def test_adjoint_dot_product_identity(gpu_lib, case, path, monkeypatch):
     lhs = np.sum((np.conj(G.astype(np.complex128)) * F.astype(np.complex128)).real)
     rhs = np.sum(f.astype(np.float64) * g.astype(np.float64))
     scale = np.sum(np.abs(G) * np.abs(F))
-    print(f"adjoint case {case} {path}: <Ff,G> = {lhs:.9e}, <f,A G> = {rhs:.9e}, rel {abs(lhs - rhs) / scale:.2e}")
+    print(f"adjoint case {case} {path} {boundary}: <Ff,G> = {lhs:.9e}, <f,A G> = {rhs:.9e}, "
+          f"rel {abs(lhs - rhs) / scale:.2e}")
     assert abs(lhs - rhs) <= 1e-6 * scale
 
 
@@ -72,8 +79,10 @@ def test_adjoint_row_stride_and_overwrite(gpu_lib):
     bank.close()
 
 
-def test_adjoint_mirror_plan_is_unsupported(gpu_lib):
+def test_adjoint_mirror_two_pass_plan_is_unsupported(gpu_lib, monkeypatch):
+    # the transpose of the fold exists only in the matrix-core adjoint
     import torch
+    monkeypatch.setenv("LIBGABOR_ALGO", "twopass")
     bank = gpu_lib.GaborBank(16, 16, [1.0], [2.0], 4, None, 3.0, "mirror", "fp32")
     G = torch.zeros((1, 4, 16, 16), dtype=torch.complex64, device="cuda")
     with pytest.raises(gpu_lib.GaborError) as ei:
