@@ -4,8 +4,8 @@ hand-written adjoint behind ``torch.autograd.Function``.
 The forward is ``gabor_bank_apply``; the backward is
 ``gabor_bank_apply_adjoint``, which maps dL/dF (complex64, PyTorch's
 convention dL/dRe F + i dL/dIm F) to dL/df.  Both run in libgabor's HIP
-kernels; nothing here computes.  The adjoint exists for the zero boundary
-only, so the layer always plans with it.
+kernels; nothing here computes.  The mirror rule's adjoint needs every
+frequency in the fused kernel (R <= 56); the zero boundary has no limit.
 """
 from __future__ import annotations
 
@@ -65,10 +65,10 @@ class GaborLayer(torch.nn.Module):
     """
 
     def __init__(self, height, width, omegas, sigmas, n_orient=None, thetas=None, radius_sigmas=3.0,
-                 precision="fp32"):
+                 precision="fp32", boundary="zero"):
         super().__init__()
         self.bank = binding.GaborBank(height, width, omegas, sigmas, n_orient, thetas, radius_sigmas,
-                                      "zero", precision)
+                                      boundary, precision)
 
     def forward(self, x):
         if x.dim() == 2:
