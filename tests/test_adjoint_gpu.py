@@ -91,12 +91,12 @@ def test_adjoint_mirror_two_pass_plan_is_unsupported(gpu_lib, monkeypatch):
     bank.close()
 
 
-def loss_grad_gpu(gpu_lib, img, om, sg, N, th):
+def loss_grad_gpu(gpu_lib, img, om, sg, N, th, boundary="zero"):
     """Autograd gradient of L = mean |F|^2 through the layer."""
     import torch
     from paper_1704_05231_amd.autograd import GaborLayer
     H, W = img.shape
-    layer = GaborLayer(H, W, om, sg, N, th)
+    layer = GaborLayer(H, W, om, sg, N, th, boundary=boundary)
     x = torch.from_numpy(img).cuda().requires_grad_(True)
     F = layer(x)
     loss = (F.real ** 2 + F.imag ** 2).mean()
@@ -143,6 +143,34 @@ def test_autograd_gradient_matches_finite_differences(gpu_lib):
     bank.close()
     err = np.abs(fd - g[ys, xs]).max() / np.abs(g[ys, xs]).max()
     print(f"finite differences: max err / peak {err:.2e}")
+    assert err <= 5e-3
+
+
+def test_autograd_mirror_gradient_matches_finite_differences(gpu_lib):
+    # Under the mirror rule a pixel near an edge also feeds the outputs near
+    # its reflections, so each difference sums |F|^2 over every output (in
+    # FP64; the unchanged outputs are bitwise equal in both runs and cancel).
+    import torch
+    H, W = 48, 56
+    om, sg, N = [math.pi / 2, math.pi / 4], [2.0, 4.0], 8
+    img = workloads.uniform_image(H, W, 545)
+    g = loss_grad_gpu(gpu_lib, img, om, sg, N, None, "mirror")
+    bank = gpu_lib.GaborBank(H, W, om, sg, N, None, 3.0, "mirror", "fp32")
+    n = len(om) * N * H * W
+    h = 1e-3
+    xs, ys = workloads.sample_pixels(H, W, 16, 546)
+    fd = np.empty(len(xs))
+    for i, (x, y) in enumerate(zip(xs, ys)):
+        vals = []
+        for sgn in (+1, -1):
+            pert = img.copy()
+            pert[y, x] += sgn * h
+            F = bank(torch.from_numpy(pert).cuda()).cpu().numpy().astype(np.complex128)
+            vals.append(np.sum(np.abs(F) ** 2) / n)
+        fd[i] = (vals[0] - vals[1]) / (2 * h)
+    bank.close()
+    err = np.abs(fd - g[ys, xs]).max() / np.abs(g[ys, xs]).max()
+    print(f"mirror finite differences: max err / peak {err:.2e}")
     assert err <= 5e-3
 
 
