@@ -134,7 +134,11 @@ def roofline_for(form, prof, traffic):
         r = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
              "frac": round(frac_m, 4), "other": {"unit": "TFLOP/s", "achieved": round(tflops, 3),
                                                  "peak": peak_c, "frac": round(frac_c, 4)}}
-    r.update({"kernel": name, "traffic": t, "launch_ms": round(avg_s * 1e3, 5),
+    # traffic: HBM bytes per launch from the FETCH_SIZE and WRITE_SIZE counters
+    # (scaled by the copy calibration), null while the kernel sources differ
+    # from the ones the counters were taken on
+    r.update({"kernel": name, "traffic": t["hbm_bytes"] if t else None,
+              "traffic_detail": t, "launch_ms": round(avg_s * 1e3, 5),
               "algorithmic_flops_per_launch": 2 * st["real_macs"],
               "algorithmic_bytes_per_launch": st["bytes"]})
     return r
