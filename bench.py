@@ -163,9 +163,11 @@ def cpu_baseline(wl, img, target_s):
     t_small, *_ = run(n0, 7)
     n = int(min(H * W, max(n0, n0 * target_s / max(t_small, 1e-6))))
     t, xs, ys, ref = run(n, 8)
+    what = (f"every pixel ({n}, a whole step)" if n == H * W
+            else f"{n} random pixels (corners included)")
     return {"value": n * n_ch / t, "unit": UNIT, "cores": threads, "kind": "oracle",
-            "sample": f"{n} random pixels (corners included) x {n_ch} channels of the same "
-                      f"workload, FP64 direct Eq. (1), {t:.1f} s on {threads} threads"}, xs, ys, ref
+            "sample": f"{what} x {n_ch} channels of the same workload, FP64 direct Eq. (1), "
+                      f"{t:.1f} s on {threads} threads"}, xs, ys, ref
 
 
 def event_time(fn, steps, warmup):
