@@ -20,6 +20,8 @@
 // Both kernels evaluate the convolutions in correlation order against
 // reversed taps krev[T] = k(R - T), T = 0..Kp-1 (zero beyond 2R), so that
 // out(z) = sum_T in(z - R + T) krev[T].
+#include <algorithm>
+
 #include "gabor_internal.h"
 
 namespace gabor {
@@ -113,16 +115,24 @@ __global__ __launch_bounds__(kRowThreads) void k_row_fp32(
         }
     }
 
+    // Each thread holds P consecutive outputs; storing them directly would
+    // make every store instruction write lanes P elements apart (partial
+    // lines).  Each plane goes through LDS instead and leaves as contiguous
+    // lanes.
     const int64_t plane = (int64_t)H * W;
     float2* dst = J + (int64_t)plane0 * plane + (int64_t)y * W;
+    float2* st = reinterpret_cast<float2*>(lds);
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const int x = x0 + threadIdx.x * P + p;
-        if (x < W) {
+    for (int q = 0; q < NC + NR; ++q) {
+        __syncthreads();                              // the row (or the previous plane) is read
 #pragma unroll
-            for (int c = 0; c < NC; ++c) dst[c * plane + x] = make_float2(ar[c][p], ai[c][p]);
-#pragma unroll
-            for (int r = 0; r < NR; ++r) dst[(NC + r) * plane + x] = make_float2(ax[r][p], 0.0f);
+        for (int p = 0; p < P; ++p)
+            st[threadIdx.x * P + p] = q < NC ? make_float2(ar[q < NC ? q : 0][p], ai[q < NC ? q : 0][p])
+                                             : make_float2(ax[q < NC ? 0 : q - NC][p], 0.0f);
+        __syncthreads();
+        for (int i = threadIdx.x; i < seg; i += blockDim.x) {
+            const int x = x0 + i;
+            if (x < W) dst[q * plane + x] = st[i];
         }
     }
 }
@@ -229,7 +239,7 @@ hipError_t launch_row_t(const float* img, int64_t stride, int H, int W, int boun
     if (threads > kRowThreads) threads = kRowThreads;
     const int seg = threads * kRowP;
     dim3 grid((W + seg - 1) / seg, H, 1);
-    const size_t lds = sizeof(float) * (size_t)(seg + fd.Kp + 4);
+    const size_t lds = sizeof(float) * std::max((size_t)(seg + fd.Kp + 4), (size_t)(2 * seg));
     hipLaunchKernelGGL((k_row_fp32<NC, NR>), grid, dim3(threads), lds, stream, img, stride, H, W,
                        boundary, fd.R, fd.Kp, d_taps + g.tap_off, d_J, g.plane0, (const BatchImage*)nullptr);
     return hipGetLastError();
@@ -242,7 +252,7 @@ hipError_t launch_row_batch_t(const BatchImage* d_imgs, int n_images, int max_h,
 {
     const int seg = kRowThreads * kRowP;
     dim3 grid((max_w + seg - 1) / seg, max_h, n_images);
-    const size_t lds = sizeof(float) * (size_t)(seg + fd.Kp + 4);
+    const size_t lds = sizeof(float) * std::max((size_t)(seg + fd.Kp + 4), (size_t)(2 * seg));
     hipLaunchKernelGGL((k_row_fp32<NC, NR>), grid, dim3(kRowThreads), lds, stream, (const float*)nullptr,
                        (int64_t)0, 0, 0, boundary, fd.R, fd.Kp, d_taps + g.tap_off, d_J, g.plane0, d_imgs);
     return hipGetLastError();
