@@ -64,8 +64,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default=",".join(FORMS))
     ap.add_argument("--no-tune", action="store_true", help="keep the default segment heights")
-    ap.add_argument("--workloads", default="lsdft,batch,layer,iir",
-                    help="secondary workloads reported under 'workloads' (lsdft, batch, layer, iir; empty: none)")
+    ap.add_argument("--workloads", default="lsdft,sdft,batch,layer,iir",
+                    help="secondary workloads reported under 'workloads' (lsdft, sdft, batch, layer, iir; "
+                         "empty: none)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run a plain device-to-device copy of MIB MiB instead (counter calibration)")
     return ap.parse_args()
@@ -217,6 +218,27 @@ def bench_lsdft(binding, workloads, steps, warmup):
     res["algorithmic_bytes"] = nbytes
     res["algorithmic_real_macs"] = macs
     return res
+
+
+def bench_sdft_box(binding, workloads, steps, warmup):
+    """512^2 uniform image, 16 x 16 box window, all 256 bins, zero boundary:
+    one sdft_box_apply launch per step (FP64 recursion, complex64 output)."""
+    import oracle
+    import torch
+    wl = workloads.sdft_box_512()
+    img = torch.from_numpy(wl.image).cuda()
+    H, W = wl.image.shape
+    out = torch.empty((wl.my, wl.mx, H, W), dtype=torch.complex64, device="cuda")
+    nbytes = 4 * H * W + 8 * wl.my * wl.mx * H * W
+    xs, ys = workloads.sample_pixels(H, W, 300, 33)
+    ref = oracle.lsdft_points(wl.image, wl.my, wl.mx, wl.sigma, xs, ys, wl.boundary)
+    ms = event_time(lambda: binding.sdft_box(img, wl.my, wl.mx, wl.boundary, out=out), steps * 4, warmup)
+    got = out.cpu().numpy()[:, :, ys, xs].transpose(2, 0, 1)
+    return {"workload": wl.name, "outputs_per_call": wl.my * wl.mx * H * W, "unit": UNIT,
+            "ms": round(ms, 5), "value": wl.my * wl.mx * H * W / (ms * 1e-3),
+            "max_abs_err_over_max_f": float(np.abs(got - ref).max() / np.abs(wl.image).max()),
+            "max_rel_err_per_bin": float((np.abs(got - ref).max(0) / np.abs(ref).max(0)).max()),
+            "algorithmic_bytes": nbytes, "roofline": hbm_roofline(nbytes, ms, "one launch per call")}
 
 
 def bench_batch(binding, workloads, steps, warmup):
@@ -421,7 +443,7 @@ def main():
         line["bf16_split_vs_fp32"] = round(forms["bf16_split"]["value"] / forms["fp32"]["value"], 3)
     extra = {}
     for name in [w for w in args.workloads.split(",") if w]:
-        extra[name] = {"lsdft": bench_lsdft, "batch": bench_batch, "layer": bench_layer, "iir": bench_iir}[name](
+        extra[name] = {"lsdft": bench_lsdft, "sdft": bench_sdft_box, "batch": bench_batch, "layer": bench_layer, "iir": bench_iir}[name](
             binding, workloads, max(5, args.steps // 10), max(2, args.warmup // 5))
         print(f"bench.py: {name} done", file=sys.stderr, flush=True)
     if extra:

@@ -238,6 +238,41 @@ gabor_status lsdft_apply(const float* d_image, int32_t height, int32_t width,
                          void* hip_stream);
 
 /*
+ * sdft_box_apply -- box-window 2-D sliding DFT of one image by the
+ * circular-shift recursion (Sec. I; Eq. (17) with a uniform window, the
+ * conventional SDFT the paper builds on):
+ *
+ *   F_{u,v}(x,y) = 1/(Mx My) sum_{j<Mx} sum_{i<My} f(x - Mx/2 + j, y - My/2 + i)
+ *                  exp(-i 2 pi (u j / Mx + v i / My))
+ *
+ * for every pixel and bin u = 0..m_x-1, v = 0..m_y-1 (M/2 rounds down).  With
+ * C_v(m) the My-point DFT of column m over the window rows, moving the window
+ * one column right gives
+ *   F(x+1) = exp(i 2 pi u / Mx) (F(x) + (C_v(x - Mx/2 + Mx) - C_v(x - Mx/2)) / Mx).
+ * The column DFTs are direct FP64 sums; the recursion state is FP64 and is
+ * re-anchored by a direct FP64 window sum every 8 columns, so the only
+ * single-precision step is the final rounding to complex64.  Bins with
+ * 0 < v < My/2 give their conjugate partners (Mx-u mod Mx, My-v).  Same
+ * output as lsdft_apply with an infinite sigma.
+ *
+ *   d_image           device FP32 image, height x width, row stride
+ *                     row_stride_elems (>= width).
+ *   m_y, m_x          window rows and columns, 1 .. 64 each.
+ *   boundary          rule for samples outside the image.
+ *   d_out             device complex64 output, layout [m_y][m_x][H][W]
+ *                     (plane v * m_x + u), m_y*m_x*H*W*8 bytes, fully
+ *                     overwritten.
+ *
+ * One kernel launch on hip_stream; nothing is allocated (twiddle tables
+ * travel as launch arguments), so it may be captured in a HIP graph.
+ * Widths above 8192 (the row of FP64 column DFTs lives in on-chip memory),
+ * heights above 65535 or windows above 64 return GABOR_ERR_UNSUPPORTED.
+ */
+gabor_status sdft_box_apply(const float* d_image, int32_t height, int32_t width,
+                            int64_t row_stride_elems, int32_t m_y, int32_t m_x,
+                            gabor_boundary boundary, void* d_out, void* hip_stream);
+
+/*
  * lsdft_work -- algorithmic work of one lsdft_apply (host arithmetic only):
  * real multiply-adds counted as M taps per real 1-D pass per pixel over the
  * computed bins, and bytes as one read of the image plus one write of every

@@ -6,9 +6,10 @@ current HIP stream.  There is no fallback: if libgabor.so is missing or no
 GPU is visible, calls raise.
 
 The functions keep the C names: ``gabor_bank_plan``, ``gabor_bank_apply``,
-``gabor_bank_destroy``, ``lsdft_apply``, ``lsdft_work``,
+``gabor_bank_destroy``, ``lsdft_apply``, ``lsdft_work``, ``sdft_box_apply``,
 ``gabor_bank_plan_info``, ``gabor_status_string``.  ``GaborBank`` wraps a
-plan for torch tensors, ``lsdft`` wraps ``lsdft_apply``.
+plan for torch tensors, ``lsdft`` wraps ``lsdft_apply`` and ``sdft_box``
+wraps ``sdft_box_apply``.
 """
 from __future__ import annotations
 
@@ -31,7 +32,7 @@ PRECISION = {"fp32": 0, "bf16_split": 1, "fp16_split": 2, "bf16": 3, "fp16": 4}
 EXPORTS = ["gabor_status_string", "gabor_bank_plan", "gabor_bank_plan_iir", "gabor_bank_apply", "gabor_bank_apply_adjoint",
            "gabor_bank_destroy", "gabor_batch_create", "gabor_batch_apply", "gabor_batch_info",
            "gabor_batch_destroy", "gabor_bank_autotune", "gabor_bank_get_tuning", "gabor_bank_set_tuning",
-           "lsdft_apply", "lsdft_work", "gabor_bank_plan_info", "gabor_profile_enable",
+           "lsdft_apply", "lsdft_work", "sdft_box_apply", "gabor_bank_plan_info", "gabor_profile_enable",
            "gabor_profile_read"]
 
 
@@ -103,6 +104,8 @@ def load():
     lib.lsdft_apply.restype = ctypes.c_int
     lib.lsdft_work.argtypes = [i32, i32, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.lsdft_work.restype = ctypes.c_int
+    lib.sdft_box_apply.argtypes = [P, i32, i32, i64, i32, i32, ctypes.c_int, P, P]
+    lib.sdft_box_apply.restype = ctypes.c_int
     lib.gabor_profile_enable.argtypes = [P, i32]
     lib.gabor_profile_enable.restype = ctypes.c_int
     lib.gabor_profile_read.argtypes = [P, ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
@@ -262,6 +265,29 @@ def lsdft(img, m_y, m_x, sigma, boundary="zero", precision="fp32", out=None, str
         raise ValueError("out must be a contiguous complex64 [m_y, m_x, H, W] tensor")
     lsdft_apply(img.data_ptr(), H, W, img.stride(0), m_y, m_x, sigma, boundary, precision,
                 out.data_ptr(), stream)
+    return out
+
+
+def sdft_box_apply(d_image: int, height, width, row_stride_elems, m_y, m_x, boundary="zero",
+                   d_out: int = 0, stream=None):
+    st = load().sdft_box_apply(ctypes.c_void_p(d_image), int(height), int(width), int(row_stride_elems),
+                               int(m_y), int(m_x), BOUNDARY[boundary], ctypes.c_void_p(d_out),
+                               _stream(stream))
+    _check(st, "sdft_box_apply")
+
+
+def sdft_box(img, m_y, m_x, boundary="zero", out=None, stream=None):
+    """Box-window sliding DFT of a (H, W) float32 GPU tensor (row stride may
+    exceed W): complex64 [m_y, m_x, H, W], bin (v, u) at out[v, u]."""
+    import torch
+    if img.dtype != torch.float32 or img.dim() != 2 or not img.is_cuda or img.stride(1) != 1:
+        raise ValueError("image must be a row-major 2-D float32 GPU tensor")
+    H, W = img.shape
+    if out is None:
+        out = torch.empty((m_y, m_x, H, W), dtype=torch.complex64, device=img.device)
+    elif out.dtype != torch.complex64 or not out.is_contiguous() or tuple(out.shape) != (m_y, m_x, H, W):
+        raise ValueError("out must be a contiguous complex64 [m_y, m_x, H, W] tensor")
+    sdft_box_apply(img.data_ptr(), H, W, img.stride(0), m_y, m_x, boundary, out.data_ptr(), stream)
     return out
 
 

@@ -110,6 +110,18 @@ def lsdft_512(seed: int = 3) -> LsdftWorkload:
                          16, 16, 4.0, ZERO)
 
 
+# Window scale at which every Gaussian weight exp(-t^2 / (2 sigma^2)), |t| <= 64,
+# rounds to exactly 1 in FP64: the localized SDFT with this sigma is the
+# box-window SDFT.
+BOX_SIGMA = 1e30
+
+
+def sdft_box_512(seed: int = 3) -> LsdftWorkload:
+    """The image of lsdft_512 (512 x 512 uniform); 16 x 16 box window; all
+    256 bins; zero boundary.  sigma is BOX_SIGMA for the oracle."""
+    return LsdftWorkload("sdft-box-512sq-16x16", uniform_image(512, 512, seed), 16, 16, BOX_SIGMA, ZERO)
+
+
 def batch_sizes(n: int = 256, lo: int = 64, hi: int = 1024, seed: int = 4):
     """Side lengths drawn i.i.d. uniform on [lo, hi] inclusive (h, w independent)."""
     rng = np.random.Generator(np.random.PCG64(seed))

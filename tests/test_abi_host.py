@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_functions():
     text = open(os.path.join(ROOT, "include", "libgabor.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(gabor_\w+|lsdft_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(gabor_\w+|lsdft_\w+|sdft_\w+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -166,3 +166,24 @@ def test_iir_plan_rejects_bad_arguments():
     assert lib.gabor_bank_plan_iir(ctypes.byref(plan), 8, 8, 1, P(om), P(sg), 4, None, 3, None) == 1
     # sigma below the recursive design's range: valid but unsupported, before any allocation
     assert lib.gabor_bank_plan_iir(ctypes.byref(plan), 8, 8, 1, P(om), P(np.array([0.3])), 4, None, 0, None) == 4
+
+
+def _sdft_raw(img=16, H=8, W=8, stride=8, my=4, mx=4, bnd=0, out=16):
+    lib = binding.load()
+    return lib.sdft_box_apply(None if img is None else ctypes.c_void_p(img), H, W, stride, my, mx, bnd,
+                              None if out is None else ctypes.c_void_p(out), None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(img=None), dict(out=None), dict(H=0), dict(W=-1), dict(stride=7), dict(my=0), dict(mx=-2),
+    dict(bnd=2), dict(bnd=-1),
+])
+def test_sdft_box_rejects_bad_arguments(kw):
+    # rejected on the host: the fake device pointers are never touched
+    assert _sdft_raw(**kw) == 1
+
+
+@pytest.mark.parametrize("kw", [dict(my=65), dict(mx=100), dict(W=8193, stride=8193),
+                                dict(H=65536, W=2, stride=2)])
+def test_sdft_box_limits_are_unsupported(kw):
+    assert _sdft_raw(**kw) == 4

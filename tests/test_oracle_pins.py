@@ -268,6 +268,27 @@ def test_lsdft_box_window_is_conventional_sdft_and_symmetric():
     assert np.abs(F[0, 0].imag).max() < 1e-15
 
 
+@pytest.mark.parametrize("boundary", ["zero", "mirror"])
+def test_lsdft_at_box_sigma_is_the_exact_box_sdft(boundary):
+    """At sigma = 1e30 every window weight is exactly 1/M, so the oracle is
+    the box-window SDFT (the conventional SDFT of Sec. I) at every pixel:
+    fft2 of each pixel's window patch, gathered by the boundary rule, over
+    My Mx.  Odd and even M, and a window wider than the image."""
+    H, W = 9, 7
+    img = workloads.uniform_image(H, W, 21)
+    for (my, mx) in [(5, 4), (3, 9)]:
+        F = oracle.lsdft(img, my, mx, workloads.BOX_SIGMA, boundary)
+        for y in range(H):
+            for x in range(W):
+                patch = np.zeros((my, mx))
+                for i in range(my):
+                    for j in range(mx):
+                        r, c = fold(y - my // 2 + i, H, boundary), fold(x - mx // 2 + j, W, boundary)
+                        if r >= 0 and c >= 0:
+                            patch[i, j] = img[r, c]
+                np.testing.assert_allclose(F[:, :, y, x], np.fft.fft2(patch) / (my * mx), rtol=0, atol=1e-15)
+
+
 def test_lsdft_bin_is_a_gabor_channel():
     """Odd M: window offsets are symmetric, |d| <= (M-1)/2, so bin (u, v)
     equals exp(-i w0 (u + v) h) times the Gabor output of Eq. (1) at
