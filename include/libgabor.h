@@ -8,7 +8,8 @@
  * 1-D Gabor pass (Eq. (4)); the horizontal result of orientation theta is
  * reused, conjugated, for pi - theta (Eq. (13)-(16)); Algorithm 1 is the bank
  * schedule.  The localized SDFT is Eq. (17)-(18) computed the same way
- * (Eq. (19)-(26), Algorithm 2).
+ * (Eq. (19)-(26), Algorithm 2); its box-window special case, the
+ * conventional SDFT, is also computed by the circular-shift recursion.
  *
  * Conventions shared by every entry point:
  *   - Images are single-channel FP32, row-major, H rows by W columns, with a
@@ -261,7 +262,8 @@ gabor_status lsdft_apply(const float* d_image, int32_t height, int32_t width,
  *   boundary          rule for samples outside the image.
  *   d_out             device complex64 output, layout [m_y][m_x][H][W]
  *                     (plane v * m_x + u), m_y*m_x*H*W*8 bytes, fully
- *                     overwritten.
+ *                     overwritten; 8-byte aligned (16-byte aligned with an
+ *                     even width selects two-column stores).
  *
  * One kernel launch on hip_stream; nothing is allocated (twiddle tables
  * travel as launch arguments), so it may be captured in a HIP graph.

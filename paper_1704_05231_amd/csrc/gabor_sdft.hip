@@ -22,6 +22,7 @@
 // so bins with v > My/2, and with u > Mx/2 on the rows v = 0 and v = My/2,
 // are never computed.  Every output plane is written once.
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 
 #include "../../include/libgabor.h"
@@ -38,7 +39,8 @@ constexpr int kSdftMaxW = 8192;          // row length held in LDS (FP64 column 
 struct SdftArgs {
     const float* img;
     int64_t stride;
-    int32_t H, W, my, mx, boundary, pad_;
+    int32_t H, W, my, mx, boundary;
+    int32_t wide;                        // 16-byte stores: even W and a 16-byte aligned output
     float2* out;
     double twx[2][kSdftMaxM];            // cos, sin of 2 pi k / Mx
     double twy[2][kSdftMaxM];            // cos, sin of 2 pi k / My
@@ -73,7 +75,10 @@ __global__ __launch_bounds__(kSdftThreads) void k_sdft_box(SdftArgs a)
     extern __shared__ double2 sdft_lds[];
     const int y = blockIdx.x, v = blockIdx.y;
     const int W = a.W, mx = a.mx, my = a.my, hx = mx / 2, hy = my / 2;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // wave index, held in a scalar register: bins u, and with them the twiddle
+    // indices, are then wave-uniform and the tables are read by scalar loads
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n_c = (W + mx + 15) & ~15;
     double2* C = sdft_lds;                                            // C[c_slot(k)] = C_v(k - hx)
     float2* stage_all = reinterpret_cast<float2*>(C + n_c);             // one kRun x 64 block per wave
@@ -97,8 +102,11 @@ __global__ __launch_bounds__(kSdftThreads) void k_sdft_box(SdftArgs a)
         if (xx >= 0) {
 #pragma unroll 8
             for (int i = 0; i < my; ++i) {
+                // unconditional load (row 0 stands in for rows outside a zero
+                // boundary) and a select, so the unrolled loads issue together
                 const int64_t ro = row_off[i];
-                const double f = ro < 0 ? 0.0 : (double)a.img[ro + xx];
+                const float raw = a.img[(ro < 0 ? 0 : ro) + xx];
+                const double f = ro < 0 ? 0.0 : (double)raw;
                 const double2 tw = row_tw[i];
                 cr += f * tw.x;
                 ci += f * tw.y;
@@ -156,8 +164,19 @@ __global__ __launch_bounds__(kSdftThreads) void k_sdft_box(SdftArgs a)
                 }
             }
             __syncthreads();
-            // contiguous stores of the staged columns
-            if (active) {
+            // contiguous stores of the staged columns: two columns (16 bytes)
+            // per lane when every column pair is 16-byte aligned
+            if (active && a.wide) {
+                for (int e = 2 * lane; e < 64 * kRun; e += 128) {
+                    const int x = r0 * kRun + e;
+                    if (x < W) {
+                        const float2 v0 = stage[stage_slot(e / kRun, e % kRun)];
+                        const float2 v1 = stage[stage_slot(e / kRun, e % kRun + 1)];
+                        *reinterpret_cast<float4*>(fa + x) = make_float4(v0.x, v0.y, v1.x, v1.y);
+                        if (partner) *reinterpret_cast<float4*>(fb + x) = make_float4(v0.x, -v0.y, v1.x, -v1.y);
+                    }
+                }
+            } else if (active) {
                 for (int e = lane; e < 64 * kRun; e += 64) {
                     const int x = r0 * kRun + e;
                     if (x < W) {
@@ -214,6 +233,7 @@ extern "C" gabor_status sdft_box_apply(const float* d_image, int32_t height, int
     a.mx = m_x;
     a.boundary = boundary;
     a.out = (float2*)d_out;
+    a.wide = (width % 2 == 0 && ((uintptr_t)d_out & 15) == 0) ? 1 : 0;
     sdft_table(m_x, a.twx[0], a.twx[1]);
     sdft_table(m_y, a.twy[0], a.twy[1]);
     const size_t lds = (size_t)((width + m_x + 15) & ~15) * sizeof(double2) + (size_t)4 * 64 * kRun * sizeof(float2) +

@@ -130,3 +130,20 @@ def test_sdft_box_graph_replays(gpu_lib):
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(out, eager)
+
+
+def test_sdft_box_output_alignment(gpu_lib):
+    """An output only 8-byte aligned (one complex64 element into a buffer)
+    takes one-column stores; the values are the same bits as with the
+    16-byte aligned output's two-column stores."""
+    import torch
+    img = workloads.uniform_image(30, 64, 23)
+    x = torch.from_numpy(img).cuda()
+    a = gpu_lib.sdft_box(x, 6, 8, "mirror")
+    flat = torch.full((6 * 8 * 30 * 64 + 1,), float("nan"), dtype=torch.complex64, device="cuda")
+    b = flat[1:].view(6, 8, 30, 64)
+    assert b.data_ptr() % 16 == 8
+    gpu_lib.sdft_box(x, 6, 8, "mirror", out=b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.isnan(flat[0]).item()
