@@ -168,7 +168,20 @@ def cpu_baseline(wl, img, target_s):
             else f"{n} random pixels (corners included)")
     return {"value": n * n_ch / t, "unit": UNIT, "cores": threads, "kind": "oracle",
             "sample": f"{what} x {n_ch} channels of the same workload, FP64 direct Eq. (1), "
-                      f"{t:.1f} s on {threads} threads"}, xs, ys, ref
+                      f"{t:.1f} s on {threads} threads",
+            "cpu_model": host_cpu_model(), "host_cpus": os.cpu_count()}, xs, ys, ref
+
+
+def host_cpu_model():
+    """The host CPU's model name from /proc/cpuinfo (None where unreadable)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def event_time(fn, steps, warmup):
