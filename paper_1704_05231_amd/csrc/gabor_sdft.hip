@@ -1,7 +1,7 @@
 // Box-window 2-D sliding DFT by the circular-shift recursion, re-anchored in
-// FP64.  With a uniform window (the G = 1 case of Eq. (17), which the paper
-// notes is the conventional SDFT; Sec. I describes the recursion, valid only
-// for a box window):
+// FP64.  Eq. (17) with a constant window of unit sum (the conventional SDFT
+// that the paper relates Eq. (17) to, scaled by 1/(Mx My); Sec. I describes
+// its recursion, which holds only for a box window):
 //
 //   F_{u,v}(x,y) = 1/(Mx My) sum_{j<Mx} sum_{i<My} f(x - Mx/2 + j, y - My/2 + i)
 //                  exp(-i 2 pi (u j / Mx + v i / My)).
