@@ -44,14 +44,27 @@ PEAK_TFLOPS = {"fp32_mfma": 157.3, "fp32_vector": 157.3, "bf16_mfma": 2500.0, "f
 FORMS = ["fp32", "bf16_split", "fp16_split", "bf16", "fp16", "fp32_twopass"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = ["paper_1704_05231_amd/csrc/gabor_fused.hip", "paper_1704_05231_amd/csrc/gabor_fp32.hip"]
+# HBM bytes of the box-window SDFT launch, from the same counters, keyed by its source
+SDFT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sdft-box-512sq-16x16.json")
+SDFT_SOURCES = ["paper_1704_05231_amd/csrc/gabor_sdft.hip"]
 
 
-def source_hash() -> str:
+def source_hash(sources=None) -> str:
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in sources or KERNEL_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def load_traffic(path, sources=None):
+    """Per-kernel HBM bytes per launch from a counter summary, or None when
+    the file is missing or the kernel sources changed since it was taken."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        tf = json.load(fh)
+    return tf.get("kernels", {}) if tf.get("source_hash") == source_hash(sources) else None
 
 
 def parse():
@@ -247,11 +260,15 @@ def bench_sdft_box(binding, workloads, steps, warmup):
     ref = oracle.lsdft_points(wl.image, wl.my, wl.mx, wl.sigma, xs, ys, wl.boundary)
     ms = event_time(lambda: binding.sdft_box(img, wl.my, wl.mx, wl.boundary, out=out), steps * 4, warmup)
     got = out.cpu().numpy()[:, :, ys, xs].transpose(2, 0, 1)
+    roof = hbm_roofline(nbytes, ms, "one launch per call")
+    t = (load_traffic(SDFT_TRAFFIC_FILE, SDFT_SOURCES) or {}).get("k_sdft_box")
+    if t:
+        roof.update({"traffic": t["hbm_bytes"], "traffic_detail": t})
     return {"workload": wl.name, "outputs_per_call": wl.my * wl.mx * H * W, "unit": UNIT,
             "ms": round(ms, 5), "value": wl.my * wl.mx * H * W / (ms * 1e-3),
             "max_abs_err_over_max_f": float(np.abs(got - ref).max() / np.abs(wl.image).max()),
             "max_rel_err_per_bin": float((np.abs(got - ref).max(0) / np.abs(ref).max(0)).max()),
-            "algorithmic_bytes": nbytes, "roofline": hbm_roofline(nbytes, ms, "one launch per call")}
+            "algorithmic_bytes": nbytes, "roofline": roof}
 
 
 def bench_batch(binding, workloads, steps, warmup):
@@ -401,12 +418,7 @@ def main():
         __graft_entry__.build()
     binding.load()
 
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as fh:
-            tf = json.load(fh)
-        if tf.get("source_hash") == source_hash():
-            traffic = tf.get("kernels", {})
+    traffic = load_traffic(TRAFFIC_FILE)
 
     wl = workloads.bank_1024()
     img = wl.images[0]
