@@ -147,3 +147,24 @@ def test_sdft_box_output_alignment(gpu_lib):
     torch.cuda.synchronize()
     assert torch.equal(a, b)
     assert torch.isnan(flat[0]).item()
+
+
+def draw(seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    H = int(rng.integers(1, 25))
+    W = int(rng.integers(1, 701))
+    my, mx = int(rng.integers(1, 17)), int(rng.integers(1, 17))
+    boundary = "mirror" if rng.integers(0, 2) else "zero"
+    return H, W, my, mx, boundary
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_sdft_box_random_configuration(gpu_lib, seed):
+    """Seeded random shapes (1..24 x 1..700: one or two 512-column chunks),
+    windows (1..16 per axis) and boundary rules, every output against the
+    oracle."""
+    H, W, my, mx, bnd = draw(900 + seed)
+    img = workloads.uniform_image(H, W, 1000 + seed)
+    got = gpu_sdft(gpu_lib, img, my, mx, bnd)
+    ref = oracle.lsdft(img, my, mx, BOX, bnd)
+    check(got, ref, img, f"sdft-box seed {seed}: {H}x{W} {my}x{mx} {bnd}")
