@@ -155,7 +155,8 @@ __global__ __launch_bounds__(kSdftThreads) void k_sdft_box(SdftArgs a)
                 for (int t = 0; t < kRun; ++t) {
                     stage[stage_slot(lane, t)] = make_float2((float)fr, (float)fi);
                     const int x = x0 + t;
-                    if (x + 1 < W) {
+                    // the state after the run's last column is the next lane's anchor
+                    if (t + 1 < kRun && x + 1 < W) {
                         const double2 cin = C[c_slot(x + mx)], cout = C[c_slot(x)];
                         const double gr = fr + (cin.x - cout.x) * inv_mx, gi = fi + (cin.y - cout.y) * inv_mx;
                         fr = gr * er - gi * ei;
