@@ -61,3 +61,22 @@ def test_sdft_box_512_repeats_bitwise(gpu_lib):
     runs = repeats(lambda: gpu_lib.sdft_box(img, wl.my, wl.mx, wl.boundary, out=out), out)
     for r in runs:
         assert torch.equal(torch.view_as_real(r), torch.view_as_real(runs[0]))
+
+
+@pytest.mark.parametrize("boundary", ["zero", "mirror"])
+def test_adjoint_repeats_bitwise(gpu_lib, boundary):
+    """The adjoint of the layer's 8 x 4 bank on a 512^2 image: per-job partial
+    planes summed (or folded) in a fixed job order."""
+    import math
+    import numpy as np
+    import torch
+    om = np.array([math.pi / 2, math.pi / 4, math.pi / 8, math.pi / 16])
+    bank = gpu_lib.GaborBank(512, 512, om, 0.5 * 2 * math.pi / om, 8, None, 3.0, boundary, "fp32")
+    g = torch.from_numpy(workloads.uniform_image(4 * 8 * 512, 2 * 512, 31) - 0.5).cuda()
+    grad_out = torch.view_as_complex(g.view(4, 8, 512, 512, 2)).contiguous()
+    grad_img = torch.empty((512, 512), dtype=torch.float32, device="cuda")
+    runs = repeats(lambda: bank.adjoint(grad_out, grad_img), grad_img)
+    bank.close()
+    for r in runs:
+        assert not torch.isnan(r).any()
+        assert torch.equal(r, runs[0])
