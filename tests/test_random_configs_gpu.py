@@ -43,7 +43,7 @@ def draw(seed):
     return H, W, omegas, sigmas, n_orient, boundary, prec
 
 
-@pytest.mark.parametrize("seed", range(24))
+@pytest.mark.parametrize("seed", range(96))
 def test_random_configuration(gpu_lib, seed):
     import torch
     H, W, om, sg, N, bnd, prec = draw(700 + seed)
