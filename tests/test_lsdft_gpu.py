@@ -125,3 +125,28 @@ def test_lsdft_512_sampled(gpu_lib, lsdft_512_ref, prec):
     err, peak = per_bin_err(g, ref, 0)
     print(f"lsdft-512 {prec}: sampled max per-bin rel err {err.max():.3e}")
     assert np.all(err <= tol(prec, wl.image, peak))
+
+
+def draw(seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    H = int(rng.integers(1, 41))
+    W = int(rng.integers(1, 161))
+    my, mx = int(rng.integers(1, 17)), int(rng.integers(1, 17))
+    sigma = float(rng.uniform(0.5, 8.0))
+    boundary = "mirror" if rng.integers(0, 2) else "zero"
+    prec = PRECISIONS[int(rng.integers(0, len(PRECISIONS)))]
+    return H, W, my, mx, sigma, boundary, prec
+
+
+@pytest.mark.parametrize("seed", range(32))
+def test_lsdft_random_configuration(gpu_lib, seed):
+    """Seeded random shapes (1..40 x 1..160), windows (1..16 per axis),
+    window scales, boundary rules and forms, every bin at every pixel."""
+    H, W, my, mx, sg, bnd, prec = draw(600 + seed)
+    img = workloads.uniform_image(H, W, 650 + seed)
+    got = gpu_lsdft(gpu_lib, img, my, mx, sg, bnd, prec)
+    ref = oracle.lsdft(img, my, mx, sg, bnd)
+    assert np.all(np.isfinite(got)), "a bin plane was not written"
+    err, peak = per_bin_err(got, ref, (2, 3))
+    print(f"lsdft seed {seed} {H}x{W} {my}x{mx} sigma {sg:.2f} {bnd} {prec}: max per-bin rel err {err.max():.3e}")
+    assert np.all(err <= tol(prec, img, peak))
