@@ -199,3 +199,38 @@ def test_feature_layer_workload_sampled(gpu_lib):
         err = np.abs(g[b][ys, xs] - ref).max() / np.abs(ref).max()
         print(f"layer image {b}: max err / peak {err:.2e}")
         assert err <= 1e-5
+
+
+def draw(seed):
+    """Shape, frequencies, radii, orientations and rule; the mirror rule's
+    adjoint (transpose of the fold) is on the matrix cores, which take radii
+    up to 56, the zero rule's any radius (beyond that the vector-ALU adjoint)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    H, W = int(rng.integers(1, 80)), int(rng.integers(1, 90))
+    boundary = "mirror" if rng.integers(0, 2) else "zero"
+    choices = [0, 1, 3, 6, 10, 20, 27, 30, 40, 45, 56] + ([] if boundary == "mirror" else [70, 88, 104, 110])
+    n_freq = int(rng.integers(1, 3))
+    radii = [int(rng.choice(choices)) for _ in range(n_freq)]
+    sigmas = [r / 3.0 if r > 0 else 0.1 for r in radii]
+    omegas = [float(rng.uniform(0.0, math.pi)) for _ in range(n_freq)]
+    return H, W, omegas, sigmas, int(rng.integers(1, 9)), boundary
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_adjoint_random_dot_product_identity(gpu_lib, seed):
+    """<bank(f), G> = <f, adjoint(G)> over seeded random configurations."""
+    import torch
+    H, W, om, sg, N, bnd = draw(540 + seed)
+    bank = make_bank(gpu_lib, H, W, om, sg, N, None, bnd)
+    rng = np.random.Generator(np.random.PCG64(560 + seed))
+    f = rng.uniform(-1, 1, (H, W)).astype(np.float32)
+    G = (rng.uniform(-1, 1, (len(om), N, H, W)) + 1j * rng.uniform(-1, 1, (len(om), N, H, W))).astype(np.complex64)
+    F = bank(torch.from_numpy(f).cuda()).cpu().numpy()
+    g = bank.adjoint(torch.from_numpy(G).cuda()).cpu().numpy()
+    bank.close()
+    lhs = np.sum((np.conj(G.astype(np.complex128)) * F.astype(np.complex128)).real)
+    rhs = np.sum(f.astype(np.float64) * g.astype(np.float64))
+    scale = np.sum(np.abs(G) * np.abs(F))
+    radii = [int(math.floor(3 * s + 0.5)) for s in sg]
+    print(f"adjoint seed {seed}: {H}x{W} N={N} R={radii} {bnd}: rel {abs(lhs - rhs) / scale:.2e}")
+    assert abs(lhs - rhs) <= 1e-6 * scale
