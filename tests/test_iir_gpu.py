@@ -109,3 +109,27 @@ def test_iir_plan_has_no_adjoint_or_batch(gpu_lib):
         gpu_lib.GaborBatch(bank, [torch.zeros((16, 16), device="cuda")])
     assert ei.value.status == 4
     bank.close()
+
+
+def draw(seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    H, W = int(rng.integers(1, 90)), int(rng.integers(1, 130))
+    n_freq = int(rng.integers(1, 3))
+    sigmas = [float(rng.uniform(0.5, 12.0)) for _ in range(n_freq)]
+    omegas = [float(rng.uniform(0.0, math.pi)) for _ in range(n_freq)]
+    boundary = "mirror" if rng.integers(0, 2) else "zero"
+    return H, W, omegas, sigmas, int(rng.integers(1, 9)), boundary
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_iir_random_configuration(gpu_lib, seed):
+    """Seeded random shapes (1..89 x 1..129), sigma in [0.5, 12], frequencies,
+    orientation counts and rules against the oracle's FP64 recursion."""
+    H, W, om, sg, N, bnd = draw(950 + seed)
+    img = workloads.uniform_image(H, W, 970 + seed)
+    got = gpu_iir(gpu_lib, img, om, sg, N, None, bnd)
+    ref = oracle.gabor_bank_iir(img, om, sg, workloads.orientations(N), bnd)
+    err = rel_err(got, ref)
+    print(f"iir seed {seed} {H}x{W} sigma {sg} N={N} {bnd}: max rel err {err.max():.3e}, "
+          f"worst err / bar {(err / bar(sg)).max():.3f}")
+    assert np.all(err <= bar(sg))
