@@ -82,6 +82,12 @@ def parse():
                          "empty: none)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run a plain device-to-device copy of MIB MiB instead (counter calibration)")
+    ap.add_argument("--isolate", default="", metavar="FORMS",
+                    help="instead of the bench line: run every frequency of the metric bank alone "
+                         "(one single-frequency plan each, --steps launches, no concurrency) for each "
+                         "listed form, and print their per-launch times (for counter runs)")
+    ap.add_argument("--seg-rows", default="", metavar="S0,S1,..",
+                    help="with --isolate: segment heights per frequency (default: the plan's own)")
     return ap.parse_args()
 
 
@@ -377,6 +383,42 @@ def bench_iir(binding, workloads, steps, warmup):
             "unit": UNIT, "ser_db_min": round(float(ser.min()), 2), "ser_db_max": round(float(ser.max()), 2)}
 
 
+def isolate(binding, wl, img_dev, forms, steps, warmup, seg_rows):
+    """Each frequency of the bank in a plan of its own, launched alone
+    `steps` times after `warmup`: per-launch event times with no other
+    launch sharing the chip (the frequencies of an apply run concurrently)."""
+    import torch
+    H, W = img_dev.shape
+    res = {}
+    for form in forms:
+        for i, (om, sg) in enumerate(zip(wl.omegas, wl.sigmas)):
+            bank = binding.GaborBank(H, W, [om], [sg], wl.n_orient, None, wl.radius_sigmas, wl.boundary,
+                                     precision_of(form))
+            if seg_rows:
+                bank.tuning = [seg_rows[i]]
+            out = torch.empty((1, wl.n_orient, H, W), dtype=torch.complex64, device="cuda")
+            for _ in range(warmup):
+                bank(img_dev, out)
+            torch.cuda.synchronize()
+            bank.profile(True)
+            for _ in range(steps):
+                bank(img_dev, out)
+            torch.cuda.synchronize()
+            prof = bank.profile_read()
+            bank.profile(False)
+            for name, st in prof.items():
+                avg = st["total_ms"] / st["launches"]
+                res[name] = {"form": form, "omega": om, "seg_rows": bank.tuning[0], "launches": st["launches"],
+                             "avg_ms": round(avg, 5),
+                             "tflops": round(2 * st["real_macs"] / (avg * 1e-3) / 1e12, 3),
+                             "gbs": round(st["bytes"] / (avg * 1e-3) / 1e9, 1),
+                             "real_macs": st["real_macs"], "bytes": st["bytes"]}
+            bank.close()
+            print(f"bench.py: isolated {form} omega={om:.4f} done", file=sys.stderr, flush=True)
+    print(json.dumps({"isolated_launches": res, "workload": wl.name, "kernel_source_hash": source_hash()}),
+          flush=True)
+
+
 def calibrate_copy(mib: int, steps: int):
     import torch
     n = mib * 1024 * 1024 // 4
@@ -425,6 +467,12 @@ def main():
     H, W = img.shape
     n_out = len(wl.omegas) * wl.n_orient * H * W
     img_dev = torch.from_numpy(img).cuda()
+    if args.isolate:
+        seg = [int(v) for v in args.seg_rows.split(",") if v]
+        if seg and len(seg) != len(wl.omegas):
+            sys.exit("bench.py: --seg-rows needs one height per frequency")
+        isolate(binding, wl, img_dev, [f for f in args.isolate.split(",") if f], args.steps, args.warmup, seg)
+        return
 
     forms, results = {}, {}
     for form in [f for f in args.forms.split(",") if f]:
@@ -442,13 +490,22 @@ def main():
         }
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if forms and not args.no_cpu_baseline:
         cpu, xs, ys, ref = cpu_baseline(wl, img, args.cpu_seconds)
         peak = np.abs(ref).max(0)                                  # [O, N]
         for form, res in results.items():
             got = res[:, :, ys, xs].transpose(2, 0, 1)
             forms[form]["max_rel_err_vs_oracle"] = float((np.abs(got - ref).max(0) / peak).max())
 
+    extra = {}
+    for name in [w for w in args.workloads.split(",") if w]:
+        extra[name] = {"lsdft": bench_lsdft, "sdft": bench_sdft_box, "batch": bench_batch, "layer": bench_layer, "iir": bench_iir}[name](
+            binding, workloads, max(5, args.steps // 10), max(2, args.warmup // 5))
+        print(f"bench.py: {name} done", file=sys.stderr, flush=True)
+    if not forms:
+        # secondary workloads only (--forms ""), e.g. for counter runs
+        print(json.dumps({"workloads": extra, "kernel_source_hash": source_hash()}), flush=True)
+        return
     head = forms["fp32"] if "fp32" in forms else next(iter(forms.values()))
     line = {
         "metric": METRIC, "value": head["value"], "unit": UNIT, "n_gpus": 1,
@@ -466,11 +523,6 @@ def main():
     }
     if "bf16_split" in forms and "fp32" in forms:
         line["bf16_split_vs_fp32"] = round(forms["bf16_split"]["value"] / forms["fp32"]["value"], 3)
-    extra = {}
-    for name in [w for w in args.workloads.split(",") if w]:
-        extra[name] = {"lsdft": bench_lsdft, "sdft": bench_sdft_box, "batch": bench_batch, "layer": bench_layer, "iir": bench_iir}[name](
-            binding, workloads, max(5, args.steps // 10), max(2, args.warmup // 5))
-        print(f"bench.py: {name} done", file=sys.stderr, flush=True)
     if extra:
         line["workloads"] = extra
     print(json.dumps(line), flush=True)

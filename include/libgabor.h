@@ -64,9 +64,14 @@ typedef enum gabor_precision {
     GABOR_PREC_FP32 = 0,        /* FP32 products, FP32 accumulation */
     GABOR_PREC_BF16_SPLIT = 1,  /* matrix cores: operands split hi+lo in
                                    bfloat16, three products, FP32 accumulation */
-    GABOR_PREC_FP16_SPLIT = 2,  /* as above with float16 operands */
+    GABOR_PREC_FP16_SPLIT = 2,  /* as above with float16 operands; the image
+                                   is scaled by 2^8 so that the lo parts stay
+                                   normal, so |f| must stay below 128: larger
+                                   pixel values overflow float16 and give
+                                   Inf/NaN outputs, which no status reports */
     GABOR_PREC_BF16 = 3,        /* matrix cores: one bfloat16 product */
-    GABOR_PREC_FP16 = 4         /* matrix cores: one float16 product */
+    GABOR_PREC_FP16 = 4         /* matrix cores: one float16 product; the
+                                   same |f| < 128 input range as FP16_SPLIT */
 } gabor_precision;
 
 /* Human-readable name of a status code (static storage, never NULL). */
@@ -212,9 +217,12 @@ gabor_status gabor_bank_destroy(gabor_plan plan);
  *
  * for every pixel and every bin u = 0..m_x-1, v = 0..m_y-1 (M/2 rounds down).
  * The window is the sampled Gaussian w(j) = exp(-(M/2 - j)^2 / (2 sigma^2))
- * over its M offsets, normalised to unit sum per axis.  Only the bins
- * u <= Mx/2, v <= My/2 are computed; the rest follow from conjugate symmetry
- * of the real input (Eq. (19)-(20)).  Twiddles are the FP64 values of
+ * over its M offsets, normalised to unit sum per axis.  The horizontal pass
+ * runs for u <= Mx/2 only, since J_{Mx-u} = conj(J_u) for a real input; the
+ * vertical pass runs for v <= My/2 over J_u and conj(J_u), which gives both
+ * F_{u,v} and F_{Mx-u,v} (Eq. (19)); the bins with v > My/2 are stored as
+ * the conjugates F_{Mx-u,My-v} = conj(F_{u,v}) (Eq. (20)).  Every bin plane
+ * is written exactly once.  Twiddles are the FP64 values of
  * 2 pi k / M at k = u j mod M, exact at quarter turns.
  *
  *   d_image           device FP32 image, height x width, row stride
@@ -295,8 +303,10 @@ gabor_status lsdft_work(int32_t height, int32_t width, int32_t m_y, int32_t m_x,
  * synchronises hip_stream.  get/set copy the chosen heights
  * (n = number of frequencies; 0 for frequencies on the two-pass kernels) so
  * that a caller can cache them; set rejects heights below the image height
- * that are not positive multiples of 32, and clamps the others to the image
- * height rounded up to 16.  Batches created afterwards use the new heights.
+ * that are not positive multiples of 32, and replaces every height of at
+ * least the image height by the image height rounded up to a multiple of
+ * 16 (one segment per strip).  Batches created afterwards use the new
+ * heights.
  */
 gabor_status gabor_bank_autotune(gabor_plan plan, const float* d_image, int64_t row_stride_elems,
                                  void* d_out, int32_t reps, void* hip_stream);

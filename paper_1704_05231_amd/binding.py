@@ -317,7 +317,10 @@ class GaborBank:
     """A plan bound to one image size, for torch tensors on the GPU.
 
     ``bank(img)`` takes a (H, W) float32 CUDA tensor (row stride may exceed W)
-    and returns a complex64 tensor [O, N, H, W] on the same device.
+    and returns a complex64 tensor [O, N, H, W] on the same device.  The
+    float16 forms (``fp16``, ``fp16_split``) scale the image by 2^8, so its
+    pixels must satisfy |f| < 128; larger values overflow to Inf/NaN outputs
+    without an error.
     """
 
     def __init__(self, height, width, omegas, sigmas, n_orient=None, thetas=None,

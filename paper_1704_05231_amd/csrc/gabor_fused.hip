@@ -206,7 +206,6 @@ __device__ __forceinline__ void lds_barrier()
 // instruction and the outstanding-access counts stay static.
 typedef int i2_t __attribute__((ext_vector_type(2)));
 constexpr uint32_t kOutside = 0xFFFFFFF0u;   // an offset past every resource
-constexpr uint32_t kFar = 0xC0000000u;       // past every output plane of at most 2^30 bytes
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes)
 {
@@ -493,13 +492,13 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
     // the segment end are written only in the last step of an odd step
     // count, which happens only where the segment reaches the image bottom
     // (segments are multiples of 32 rows or cover the image), so those rows
-    // lie past the plane and the range check drops them.  Columns past the
-    // image (last strip only) start at kFar, above every plane of at most
-    // 2^30 bytes and far enough from 2^32 that adding a segment's rows cannot
-    // wrap.
+    // lie past the plane (at most 31 rows past it: no 32-bit wrap for planes
+    // of at most 2^30 bytes) and the range check drops them.  Lanes of
+    // columns past the image (last strip only) store at kOutside.
     const uint32_t W8 = (uint32_t)a.W * 8u;
     const int xcol = x0 + 16 * w + o;
-    const uint32_t lane_off = xcol < a.W ? ((uint32_t)(yseg + 4 * g) * (uint32_t)a.W + (uint32_t)xcol) * 8u : kFar;
+    const bool col_live = xcol < a.W;
+    const uint32_t lane_off = ((uint32_t)(yseg + 4 * g) * (uint32_t)a.W + (uint32_t)xcol) * 8u;
     // c times the constant responses (hc + i hd)(vc + i vd) and
     // (hc - i hd)(vc + i vd); set once cs is known
     float2 dc_a = make_float2(0.f, 0.f), dc_b = dc_a;
@@ -532,7 +531,7 @@ __device__ __forceinline__ void stream_body(const StreamArgs& a, const FusedJob&
         if constexpr (F::drain) f32_mfma_drain(P1, P2, P3, P4);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const uint32_t off = lane_off + (uint32_t)(16 * s + r) * W8;
+            const uint32_t off = col_live ? lane_off + (uint32_t)(16 * s + r) * W8 : kOutside;
             const float p1 = sc(P1[r], out_s), p2 = sc(P2[r], out_s);
             const float p3 = sc(P3[r], out_s), p4 = sc(P4[r], out_s);
             i2_t va, vb;
@@ -961,7 +960,8 @@ __device__ __forceinline__ void adj_job(const AdjStreamArgs& a, const FusedJob& 
     const uint32_t W4 = (uint32_t)a.Wo * 4u;
     const __amdgpu_buffer_rsrc_t part = make_rsrc(a.part + (int64_t)job * plane_o, (uint32_t)(plane_o * 4));
     const int xcol = x0 + 16 * w + o;
-    const uint32_t lane_off = xcol < a.Wo ? ((uint32_t)(yseg + 4 * g) * (uint32_t)a.Wo + (uint32_t)xcol) * 4u : kFar;
+    const bool col_live = xcol < a.Wo;      // lanes past the grid store at kOutside
+    const uint32_t lane_off = ((uint32_t)(yseg + 4 * g) * (uint32_t)a.Wo + (uint32_t)xcol) * 4u;
 
     // vertical pass of output rows 16 s .. 16 s + 15
     auto col_pass = [&](int s) {
@@ -985,8 +985,9 @@ __device__ __forceinline__ void adj_job(const AdjStreamArgs& a, const FusedJob& 
         f32_mfma_drain(P1, P2);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, P1[r] - P2[r]), part,
-                                                  (int)(lane_off + (uint32_t)(16 * s + r) * W4), 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(
+                __builtin_bit_cast(int, P1[r] - P2[r]), part,
+                (int)(col_live ? lane_off + (uint32_t)(16 * s + r) * W4 : kOutside), 0, 0);
     };
 
     f2v xa[2 * PER_T], xb[2 * PER_T], ya[2 * PER_T], yb[2 * PER_T];
@@ -1186,7 +1187,9 @@ hipError_t launch_adjoint_stream(const AdjStreamArgs& a, int Q, hipStream_t stre
     if (a.n_jobs <= 0) return hipSuccess;
     if (!a.G || !a.part || !a.jobs || !a.taps || Q > kAdjStreamMaxQuarter || 16 + 2 * a.R > 4 * Q)
         return hipErrorInvalidValue;
-    if (a.seg_rows <= 0 || a.seg_rows % 16 != 0 || (a.seg_rows % 32 != 0 && a.seg_rows < a.H)) return hipErrorInvalidValue;
+    // the kernel walks the output grid (Ho rows): segments that end above its
+    // bottom must hold an even number of 16-row steps
+    if (a.seg_rows <= 0 || a.seg_rows % 16 != 0 || (a.seg_rows % 32 != 0 && a.seg_rows < a.Ho)) return hipErrorInvalidValue;
     if ((int64_t)a.H * a.W * 8 > (int64_t(1) << 30) || (int64_t)a.Ho * a.Wo * 4 > (int64_t(1) << 30))
         return hipErrorInvalidValue;
     if (a.Ho < a.H || a.Wo < a.W || a.off < 0 || a.n_xs * kSX < a.Wo || (int64_t)a.n_ys * a.seg_rows < a.Ho)

@@ -960,9 +960,11 @@ extern "C" gabor_status gabor_bank_set_tuning(gabor_plan p, const int32_t* seg_r
     for (int i = 0; i < n; ++i)
         if (p->launches[i].fused && seg_rows[i] < p->H && (seg_rows[i] < 32 || seg_rows[i] % 32 != 0))
             return GABOR_ERR_INVALID_ARG;    // a segment that does not cover the image: multiple of 32 rows
+    // a segment that covers the image becomes the image height rounded up
+    // to 16 rows (the kernel steps 16 rows at a time)
     const int hmax = (p->H + 15) / 16 * 16;
     for (int i = 0; i < n; ++i)
-        if (p->launches[i].fused) p->launches[i].seg_rows = std::min(seg_rows[i], hmax);
+        if (p->launches[i].fused) p->launches[i].seg_rows = seg_rows[i] >= p->H ? hmax : seg_rows[i];
     return GABOR_OK;
 }
 
