@@ -172,6 +172,27 @@ gabor_status gabor_bank_apply_adjoint(gabor_plan plan, const void* d_grad_out, f
                                       int64_t grad_row_stride_elems, void* hip_stream);
 
 /*
+ * gabor_bank_apply_adjoint_noalloc -- gabor_bank_apply_adjoint for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  Same arguments, same
+ * kernels and bit-identical results, but the workspace comes from a fixed
+ * array of 64 MiB that the library holds on each GPU it runs on (until the
+ * process ends) instead of memory the plan allocates; the call allocates
+ * nothing.  The workspace a plan needs is 4 bytes per partial-plane pixel
+ * on the matrix cores (jobs x (H + 2R) x (W + 2R) summed over the
+ * frequencies, R = 0 under the zero boundary) or 8 bytes per pixel per
+ * horizontal pass on the vector ALUs; a plan that needs more than 64 MiB
+ * returns GABOR_ERR_UNSUPPORTED before anything is enqueued.  Every call on
+ * one GPU shares that GPU's array, so calls whose executions overlap on one
+ * GPU (different streams, or different host threads) race and give wrong
+ * results; serialise them.  The first call on a device looks up the array's
+ * device address.  Plan profiling (gabor_profile_enable) does not time these
+ * launches.
+ */
+gabor_status gabor_bank_apply_adjoint_noalloc(gabor_plan plan, const void* d_grad_out, float* d_grad_image,
+                                              int64_t grad_row_stride_elems, void* hip_stream);
+
+/*
  * Batched bank: many images of uneven sizes through one plan.
  *
  * gabor_batch_create binds n_images device images (d_images[i], heights[i]

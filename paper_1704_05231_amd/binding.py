@@ -30,6 +30,7 @@ PRECISION = {"fp32": 0, "bf16_split": 1, "fp16_split": 2, "bf16": 3, "fp16": 4}
 
 # Every symbol include/libgabor.h declares; the CPU tests check the exports.
 EXPORTS = ["gabor_status_string", "gabor_bank_plan", "gabor_bank_plan_iir", "gabor_bank_apply", "gabor_bank_apply_adjoint",
+           "gabor_bank_apply_adjoint_noalloc",
            "gabor_bank_destroy", "gabor_batch_create", "gabor_batch_apply", "gabor_batch_info",
            "gabor_batch_destroy", "gabor_bank_autotune", "gabor_bank_get_tuning", "gabor_bank_set_tuning",
            "lsdft_apply", "lsdft_work", "sdft_box_apply", "gabor_bank_plan_info", "gabor_profile_enable",
@@ -82,6 +83,8 @@ def load():
     lib.gabor_bank_apply.restype = ctypes.c_int
     lib.gabor_bank_apply_adjoint.argtypes = [P, P, P, i64, P]
     lib.gabor_bank_apply_adjoint.restype = ctypes.c_int
+    lib.gabor_bank_apply_adjoint_noalloc.argtypes = [P, P, P, i64, P]
+    lib.gabor_bank_apply_adjoint_noalloc.restype = ctypes.c_int
     lib.gabor_bank_destroy.argtypes = [P]
     lib.gabor_bank_destroy.restype = ctypes.c_int
     lib.gabor_bank_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
@@ -182,6 +185,13 @@ def gabor_bank_apply_adjoint(plan, d_grad_out: int, d_grad_image: int, grad_row_
     st = load().gabor_bank_apply_adjoint(plan, ctypes.c_void_p(d_grad_out), ctypes.c_void_p(d_grad_image),
                                          int(grad_row_stride_elems), _stream(stream))
     _check(st, "gabor_bank_apply_adjoint")
+
+
+def gabor_bank_apply_adjoint_noalloc(plan, d_grad_out: int, d_grad_image: int, grad_row_stride_elems: int,
+                                     stream=None):
+    st = load().gabor_bank_apply_adjoint_noalloc(plan, ctypes.c_void_p(d_grad_out), ctypes.c_void_p(d_grad_image),
+                                                 int(grad_row_stride_elems), _stream(stream))
+    _check(st, "gabor_bank_apply_adjoint_noalloc")
 
 
 def gabor_bank_destroy(plan):

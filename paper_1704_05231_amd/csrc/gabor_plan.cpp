@@ -107,10 +107,11 @@ struct LaunchTimer {
     hipStream_t s;
     int kind = -1;
     hipEvent_t a = nullptr, b = nullptr;
-    LaunchTimer(gabor_plan plan, hipStream_t stream, const std::string& name, int64_t macs, int64_t bytes)
+    LaunchTimer(gabor_plan plan, hipStream_t stream, const std::string& name, int64_t macs, int64_t bytes,
+                bool enabled = true)
         : p(plan), s(stream)
     {
-        if (!p->prof) return;
+        if (!p->prof || !enabled) return;
         kind = kind_index(p, name, macs, bytes);
         a = take_event(p);
         b = take_event(p);
@@ -745,24 +746,49 @@ extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int
     return GABOR_OK;
 }
 
-extern "C" gabor_status gabor_bank_apply_adjoint(gabor_plan p, const void* d_grad_out, float* d_grad_image,
-                                                 int64_t grad_row_stride_elems, void* hip_stream)
+namespace gabor {
+
+// Which adjoint a plan takes and how much workspace it needs.  On the
+// matrix cores when every frequency runs in the fused kernel with a quarter
+// of at most 32: one partial plane per job (of the extended (H + 2R) x
+// (W + 2R) grid under the mirror rule, whose sum folds it back); otherwise
+// (zero boundary only) the vector-ALU kernels with one complex plane per
+// horizontal pass.
+gabor_status adjoint_workspace(gabor_plan p, bool* mfma_out, int64_t* bytes)
 {
-    if (!p || !d_grad_out || !d_grad_image) return GABOR_ERR_INVALID_ARG;
-    if (grad_row_stride_elems < p->W) return GABOR_ERR_INVALID_ARG;
     if (p->iir) return GABOR_ERR_UNSUPPORTED;
     const bool mirror = p->boundary == GABOR_BOUNDARY_MIRROR;
-    const int64_t npix = (int64_t)p->H * p->W;
-    hipStream_t stream = (hipStream_t)hip_stream;
-    // On the matrix cores when every frequency runs in the fused kernel with
-    // a quarter of at most 32: one launch per frequency over its jobs, in
-    // stream order, the first writing dL/df and the others adding to it.
-    // The mirror rule needs it: the sum then folds the extended grid.
     bool mfma = !p->launches.empty() && (!mirror || p->O <= kAdjFoldMaxFreq);
     for (const FreqLaunch& fl : p->launches)
         if (!fl.fused || fl.q > kAdjStreamMaxQuarter) mfma = false;
     if (mirror && !mfma) return GABOR_ERR_UNSUPPORTED;
     if (mfma) {
+        int64_t total = 0;
+        for (int i = 0; i < p->O; ++i) {
+            const int R = mirror ? p->freqs[i].R : 0;
+            total += (int64_t)p->launches[i].count * (p->H + 2 * R) * (p->W + 2 * R);
+        }
+        *bytes = total * (int64_t)sizeof(float);
+    } else {
+        if (adj_row_lds_bytes(p->adj_max_kp) > 160 * 1024 || adj_col_lds_bytes(p->adj_max_kp) > 160 * 1024)
+            return GABOR_ERR_UNSUPPORTED;
+        *bytes = (int64_t)p->ajobs.size() * p->H * p->W * (int64_t)sizeof(float2);
+    }
+    *mfma_out = mfma;
+    return GABOR_OK;
+}
+
+// The adjoint's launches, with the workspace the caller found (at least the
+// bytes adjoint_workspace reported; every byte of it that is read is first
+// written by the same call, so it needs no clearing).  `timed` brackets the
+// launches with profiling events when the plan's profiling is on.
+gabor_status adjoint_run(gabor_plan p, bool mfma, void* ws, const void* d_grad_out, float* d_grad_image,
+                         int64_t grad_row_stride_elems, hipStream_t stream, bool timed)
+{
+    const bool mirror = p->boundary == GABOR_BOUNDARY_MIRROR;
+    const int64_t npix = (int64_t)p->H * p->W;
+    if (mfma) {
+        float* part = static_cast<float*>(ws);
         const int n_planes = (int)p->fjobs.size();
         // partial planes: [job][H][W], or [job][H + 2R][W + 2R] for the mirror rule
         std::vector<int64_t> base(p->O);
@@ -772,18 +798,8 @@ extern "C" gabor_status gabor_bank_apply_adjoint(gabor_plan p, const void* d_gra
             base[i] = total;
             total += (int64_t)p->launches[i].count * (p->H + 2 * R) * (p->W + 2 * R);
         }
-        if (!p->d_adjP) {
-            const size_t bytes = (size_t)total * sizeof(float);
-            if (env_flag("LIBGABOR_FAIL_ALLOC")) return GABOR_ERR_OUT_OF_MEMORY;
-            const hipError_t e = hipMalloc((void**)&p->d_adjP, bytes);
-            if (e != hipSuccess) {
-                p->d_adjP = nullptr;
-                return e == hipErrorOutOfMemory ? GABOR_ERR_OUT_OF_MEMORY : GABOR_ERR_DEVICE;
-            }
-            p->workspace_bytes += (int64_t)bytes;
-        }
         LaunchTimer tm(p, stream, "adjoint_mfma_fp32", p->adj_row_macs + p->adj_col_macs,
-                       8 * (int64_t)p->O * p->N * npix + 4 * npix);
+                       8 * (int64_t)p->O * p->N * npix + 4 * npix, timed);
         // the frequencies run concurrently as in the forward apply
         const int n_aux = (int)p->aux.size();
         if (n_aux > 0 && hipEventRecord(p->fork_ev[0], stream) != hipSuccess) return GABOR_ERR_DEVICE;
@@ -795,7 +811,7 @@ extern "C" gabor_status gabor_bank_apply_adjoint(gabor_plan p, const void* d_gra
             hipStream_t ls = (j == 0 || n_aux == 0) ? stream : p->aux[(j - 1) % n_aux];
             AdjStreamArgs a{};
             a.G = (const float2*)d_grad_out;
-            a.part = p->d_adjP + base[i];
+            a.part = part + base[i];
             a.H = p->H;
             a.W = p->W;
             a.R = p->freqs[i].R;
@@ -819,7 +835,7 @@ extern "C" gabor_status gabor_bank_apply_adjoint(gabor_plan p, const void* d_gra
                 return GABOR_ERR_DEVICE;
         if (mirror) {
             AdjFoldArgs fa{};
-            fa.part = p->d_adjP;
+            fa.part = part;
             fa.grad = d_grad_image;
             fa.grad_stride = grad_row_stride_elems;
             fa.H = p->H;
@@ -828,29 +844,43 @@ extern "C" gabor_status gabor_bank_apply_adjoint(gabor_plan p, const void* d_gra
             for (int i = 0; i < p->O; ++i) fa.f[i] = AdjFoldFreq{base[i], p->freqs[i].R, p->launches[i].count};
             return launch_adjoint_fold_sum(fa, stream) == hipSuccess ? GABOR_OK : GABOR_ERR_DEVICE;
         }
-        return launch_adjoint_sum(p->d_adjP, n_planes, p->H, p->W, d_grad_image, grad_row_stride_elems, stream) ==
+        return launch_adjoint_sum(part, n_planes, p->H, p->W, d_grad_image, grad_row_stride_elems, stream) ==
                        hipSuccess
                    ? GABOR_OK
                    : GABOR_ERR_DEVICE;
     }
-    if (adj_row_lds_bytes(p->adj_max_kp) > 160 * 1024 || adj_col_lds_bytes(p->adj_max_kp) > 160 * 1024)
-        return GABOR_ERR_UNSUPPORTED;
-    if (!p->d_adjJ) {
-        const size_t bytes = p->ajobs.size() * (size_t)npix * sizeof(float2);
-        if (env_flag("LIBGABOR_FAIL_ALLOC")) return GABOR_ERR_OUT_OF_MEMORY;
-        const hipError_t e = hipMalloc((void**)&p->d_adjJ, bytes);
-        if (e != hipSuccess) {
-            p->d_adjJ = nullptr;
-            return e == hipErrorOutOfMemory ? GABOR_ERR_OUT_OF_MEMORY : GABOR_ERR_DEVICE;
-        }
-        p->workspace_bytes += (int64_t)bytes;
-    }
     LaunchTimer tm(p, stream, "adjoint_fp32", p->adj_row_macs + p->adj_col_macs,
-                   8 * (int64_t)p->O * p->N * npix + 4 * npix);
+                   8 * (int64_t)p->O * p->N * npix + 4 * npix, timed);
     return launch_adjoint((const float2*)d_grad_out, p->H, p->W, p->d_ajobs, (int)p->ajobs.size(), p->adj_max_kp,
-                          p->d_taps, p->d_adjJ, d_grad_image, grad_row_stride_elems, stream) == hipSuccess
+                          p->d_taps, static_cast<float2*>(ws), d_grad_image, grad_row_stride_elems, stream) ==
+                   hipSuccess
                ? GABOR_OK
                : GABOR_ERR_DEVICE;
+}
+
+}  // namespace gabor
+
+extern "C" gabor_status gabor_bank_apply_adjoint(gabor_plan p, const void* d_grad_out, float* d_grad_image,
+                                                 int64_t grad_row_stride_elems, void* hip_stream)
+{
+    if (!p || !d_grad_out || !d_grad_image) return GABOR_ERR_INVALID_ARG;
+    if (grad_row_stride_elems < p->W) return GABOR_ERR_INVALID_ARG;
+    bool mfma = false;
+    int64_t bytes = 0;
+    const gabor_status st = adjoint_workspace(p, &mfma, &bytes);
+    if (st != GABOR_OK) return st;
+    // the plan keeps its adjoint workspace from the first call on
+    if (mfma ? !p->d_adjP : !p->d_adjJ) {
+        if (env_flag("LIBGABOR_FAIL_ALLOC")) return GABOR_ERR_OUT_OF_MEMORY;
+        void* d = nullptr;
+        const hipError_t e = hipMalloc(&d, (size_t)bytes);
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? GABOR_ERR_OUT_OF_MEMORY : GABOR_ERR_DEVICE;
+        if (mfma) p->d_adjP = static_cast<float*>(d);
+        else p->d_adjJ = static_cast<float2*>(d);
+        p->workspace_bytes += bytes;
+    }
+    void* ws = mfma ? static_cast<void*>(p->d_adjP) : static_cast<void*>(p->d_adjJ);
+    return adjoint_run(p, mfma, ws, d_grad_out, d_grad_image, grad_row_stride_elems, (hipStream_t)hip_stream, true);
 }
 
 // Segment heights the tuner tries for one fused launch: multiples of 16 up

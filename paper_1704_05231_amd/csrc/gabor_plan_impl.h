@@ -76,3 +76,12 @@ struct gabor_plan_s {
     std::vector<gabor_kernel_stat> stats;
 };
 
+namespace gabor {
+// Adjoint of the bank (gabor_plan.cpp): which kernels a plan's adjoint runs
+// (mfma: the matrix-core kernels) and the workspace bytes they need; then
+// the launches with a caller-provided workspace of at least that size.
+gabor_status adjoint_workspace(gabor_plan p, bool* mfma, int64_t* bytes);
+gabor_status adjoint_run(gabor_plan p, bool mfma, void* ws, const void* d_grad_out, float* d_grad_image,
+                         int64_t grad_row_stride_elems, hipStream_t stream, bool timed);
+}  // namespace gabor
+

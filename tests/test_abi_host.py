@@ -132,6 +132,7 @@ def test_lsdft_work_counts():
 def test_adjoint_rejects_null_arguments():
     lib = binding.load()
     assert lib.gabor_bank_apply_adjoint(None, ctypes.c_void_p(16), ctypes.c_void_p(16), 8, None) == 1
+    assert lib.gabor_bank_apply_adjoint_noalloc(None, ctypes.c_void_p(16), ctypes.c_void_p(16), 8, None) == 1
 
 
 def test_batch_rejects_null_arguments():
