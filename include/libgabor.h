@@ -204,9 +204,10 @@ gabor_status gabor_bank_apply_adjoint_noalloc(gabor_plan plan, const void* d_gra
  * the batch; a batch shares its plan's streams and workspace, so the two are
  * not used concurrently.
  *
- * gabor_batch_apply runs Algorithm 1 on every bound image: one persistent
- * launch per operand size of the fused kernel, each over the tiles of all
- * images, plus FP32 two-pass launches over all images for frequencies
+ * gabor_batch_apply runs Algorithm 1 on every bound image: one launch per
+ * operand size of the fused kernel, each over the tiles of all images in
+ * decreasing order of cost, plus FP32 two-pass launches over all images for
+ * frequencies
  * outside the fused kernel's range (R > 104, or planes of more than 2^27
  * pixels; their intermediate planes live in a batch-owned workspace allocated
  * by gabor_batch_create).  It allocates and copies nothing, so it may be

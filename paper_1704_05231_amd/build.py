@@ -25,7 +25,8 @@ SOURCES = ([("gabor_plan.cpp", [], "gabor_plan"), ("gabor_lsdft.cpp", [], "gabor
             ("gabor_fp32.hip", [], "gabor_fp32"), ("gabor_adjoint.hip", [], "gabor_adjoint"),
             ("gabor_iir.hip", [], "gabor_iir"), ("gabor_sdft.hip", [], "gabor_sdft"),
             ("gabor_noalloc.hip", [], "gabor_noalloc")]
-           + [("gabor_fused.hip", [f"-DGABOR_FORM={k}"], f"gabor_fused_{k}") for k in range(5)])
+           + [("gabor_fused.hip", [f"-DGABOR_FORM={k}"], f"gabor_fused_{k}") for k in range(5)]
+           + [("gabor_ws.hip", [f"-DGABOR_FORM={k}"], f"gabor_ws_{k}") for k in range(5)])
 ARCH = "gfx950"
 
 

@@ -3,10 +3,15 @@
 // a tile table; gabor_batch_apply then only launches, so it allocates and
 // copies nothing and may be captured in a HIP graph and replayed.
 //
-// Frequencies on the fused kernel are grouped by operand quarter Q; each
-// group is one persistent launch over the tiles (image, job, strip segment)
-// of every image, ordered by decreasing length so that the last round of
-// workgroups is short.  Frequencies outside the fused kernel's range run the
+// Frequencies on the fused kernels are grouped by operand quarter Q; each
+// group is one launch over the tiles (image, job, strip segment) of every
+// image, sorted by decreasing cost.  On the wave-specialised kernel tile b
+// is workgroup b, so the dispatcher hands out the longest tiles first and
+// the rest as workgroups free up; quarters beyond it run the persistent
+// four-wave kernel, each workgroup striding over the table.  One kernel
+// over all quarters would carry the largest quarter's registers and LDS
+// into every tile (measured: 185 to 256 registers with spills against 124
+// to 177 per quarter), so each quarter keeps a launch of its own.  Frequencies outside the fused kernel's range run the
 // FP32 two-pass kernels on the caller's stream, one launch per pass over all
 // images, each image with J planes of its own in a batch-owned workspace.
 #include <algorithm>
@@ -91,19 +96,9 @@ extern "C" gabor_status gabor_batch_create(gabor_batch* out, gabor_plan p, int32
         im.n_xs = (widths[i] + sx - 1) / sx;
         b->images.push_back(im);
     }
-    std::vector<BatchFreq> freqs(p->O);
-    for (int f = 0; f < p->O; ++f) {
-        const FreqLaunch& fl = p->launches[f];
-        BatchFreq& bf = freqs[f];
-        bf.R = p->freqs[f].R;
-        bf.seg_rows = fl.seg_rows;
-        bf.in_scale = fl.in_scale;
-        bf.mid_scale = fl.mid_scale;
-        bf.out_scale = fl.out_scale;
-        bf.tap_scale[0] = fl.tap_scale[0];
-        bf.tap_scale[1] = fl.tap_scale[1];
-        if (!fl.fused) b->twopass_freqs.push_back(f);
-    }
+    const std::vector<BatchFreq> freqs = batch_freq_table(p);
+    for (int f = 0; f < p->O; ++f)
+        if (!p->launches[f].fused) b->twopass_freqs.push_back(f);
     // Tiles per quarter: image-major, then segment, strip and job (jobs of a
     // strip share its image rows), then stably sorted by decreasing length.
     std::vector<int> qs;
@@ -115,7 +110,7 @@ extern "C" gabor_status gabor_batch_create(gabor_batch* out, gabor_plan p, int32
         BatchGroup g{};
         g.q = q;
         g.first_tile = (int)tiles.size();
-        std::vector<std::pair<int, BatchTile>> tl;        // (steps, tile)
+        std::vector<std::pair<int64_t, BatchTile>> tl;    // (cost, tile)
         for (int i = 0; i < n_images; ++i)
             for (int f = 0; f < p->O; ++f) {
                 const FreqLaunch& fl = p->launches[f];
@@ -127,13 +122,19 @@ extern "C" gabor_status gabor_batch_create(gabor_batch* out, gabor_plan p, int32
                     const int steps = (std::min(seg, h - ys * seg) + 15) / 16 + lead;
                     for (int xs = 0; xs < b->images[i].n_xs; ++xs)
                         for (int j = 0; j < fl.count; ++j) {
+                            // cost: steps times the products per step of the job
+                            // kind (horizontal 2, or 1 for a real J; vertical 4,
+                            // or 2 with a real J or real taps) plus a fixed
+                            // per-step overhead
+                            const FusedJob& jb = p->fjobs[fl.first + j];
+                            const int per = q * ((jb.j_real ? 1 : 2) + (jb.j_real || jb.c_real ? 2 : 4)) + 16;
                             BatchTile t{};
                             t.image = i;
                             t.job = fl.first + j;
                             t.freq = f;
                             t.rest = xs + ys * b->images[i].n_xs;
-                            tl.push_back({steps, t});
-                            g.weight += steps;
+                            tl.push_back({(int64_t)steps * per, t});
+                            g.weight += (int64_t)steps * per;
                         }
                 }
             }
@@ -147,7 +148,7 @@ extern "C" gabor_status gabor_batch_create(gabor_batch* out, gabor_plan p, int32
         b->groups.push_back(g);
     }
     std::stable_sort(b->groups.begin(), b->groups.end(),
-                     [](const BatchGroup& a, const BatchGroup& c) { return a.weight * a.q > c.weight * c.q; });
+                     [](const BatchGroup& a, const BatchGroup& c) { return a.weight > c.weight; });
     b->tiles = (int64_t)tiles.size();
 
     hipStream_t stream = (hipStream_t)hip_stream;
@@ -181,15 +182,28 @@ extern "C" gabor_status gabor_batch_apply(gabor_batch b, void* hip_stream)
     // Fork: launch j > 0 goes to auxiliary stream (j - 1) mod n after the
     // work already queued on the caller's stream.
     const int n_aux = (int)p->aux.size();
-    if (n_aux > 0 && b->groups.size() > 1) {
+    const bool fork = n_aux > 0 && b->groups.size() > 1;
+    if (fork) {
         if (hipEventRecord(p->fork_ev[0], stream) != hipSuccess) return GABOR_ERR_DEVICE;
         for (int k = 0; k < n_aux; ++k)
             if (hipStreamWaitEvent(p->aux[k], p->fork_ev[0], 0) != hipSuccess) return GABOR_ERR_DEVICE;
     }
-    const bool fork = n_aux > 0 && b->groups.size() > 1;
     for (size_t j = 0; j < b->groups.size(); ++j) {
         const BatchGroup& g = b->groups[j];
         hipStream_t ls = (j == 0 || !fork) ? stream : p->aux[(j - 1) % n_aux];
+        if (p->use_ws && ws_supported(p->fused_op, g.q)) {
+            // one workgroup per tile, tiles in decreasing cost
+            WsTilesArgs t{};
+            t.images = b->d_images;
+            t.freqs = b->d_freqs;
+            t.tiles = b->d_tiles + g.first_tile;
+            t.jobs = p->d_fjobs;
+            t.taps = p->d_taps;
+            t.n_tiles = g.n_tiles;
+            t.boundary = p->boundary;
+            if (launch_ws_tiles(p->fused_op, t, g.q, ls) != hipSuccess) return GABOR_ERR_DEVICE;
+            continue;
+        }
         BatchArgs a{};
         a.images = b->d_images;
         a.freqs = b->d_freqs;

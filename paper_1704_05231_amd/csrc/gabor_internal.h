@@ -121,7 +121,7 @@ struct BatchImage {
 struct BatchFreq {
     int32_t R, seg_rows;
     float in_scale, mid_scale, out_scale, tap_scale[2];
-    int32_t pad_;
+    int32_t q;                 // operand quarter (contracted length 4q)
 };
 struct BatchTile {
     int32_t image, job, freq;  // job indexes the plan's fused job table
@@ -148,6 +148,27 @@ struct LsdftTaps {
     double tw[2][2][kLsdftMaxM];       // cos, sin of 2 pi k / M, k = 0..M-1 (exact at quarter turns)
 };
 
+// Wave-specialised streaming kernel (gabor_ws.hip): the same jobs and
+// results as launch_stream, eight waves per workgroup (four on the
+// horizontal pass, four on the vertical one), quarters up to kWsMaxQuarter,
+// segments of any multiple of 16 rows.
+constexpr int kWsMaxQuarter = 32;
+bool ws_supported(int op, int Q);
+hipError_t launch_ws(int op, const StreamArgs& a, int Q, hipStream_t stream);
+size_t ws_lds_bytes(int op, int Q);
+
+// The same kernel over a tile table (batches): workgroup b takes tile b,
+// every tile of one quarter Q; tiles sorted by decreasing cost.
+struct WsTilesArgs {
+    const BatchImage* images;
+    const BatchFreq* freqs;
+    const BatchTile* tiles;
+    const FusedJob* jobs;
+    const float* taps;
+    int32_t n_tiles, boundary;
+};
+hipError_t launch_ws_tiles(int op, const WsTilesArgs& t, int Q, hipStream_t stream);
+
 int stream_quarter(int op, int R);             // Q for radius R (L = 4Q >= 16 + 2R)
 size_t stream_lds_bytes(int op, int Q);
 int stream_strip_width();
@@ -160,8 +181,12 @@ template <int OP> hipError_t stream_form(const StreamArgs& a, int Q, int n_block
 template <int OP> hipError_t lsdft_form(const StreamArgs& a, const LsdftTaps& t, int Q, int n_blocks,
                                         hipStream_t stream);
 template <int OP> hipError_t batch_form(const BatchArgs& b, int Q, hipStream_t stream);
+template <int OP> hipError_t ws_form(const StreamArgs& a, int Q, int n_blocks, hipStream_t stream);
+template <int OP> hipError_t ws_tiles_form(const WsTilesArgs& t, int Q, hipStream_t stream);
 #define GABOR_DECLARE_FORM(OP)                                                                   \
     template <> hipError_t stream_form<OP>(const StreamArgs&, int, int, hipStream_t);            \
+    template <> hipError_t ws_form<OP>(const StreamArgs&, int, int, hipStream_t);                \
+    template <> hipError_t ws_tiles_form<OP>(const WsTilesArgs&, int, hipStream_t);              \
     template <> hipError_t lsdft_form<OP>(const StreamArgs&, const LsdftTaps&, int, int, hipStream_t); \
     template <> hipError_t batch_form<OP>(const BatchArgs&, int, hipStream_t);
 GABOR_DECLARE_FORM(FUSED_F32)

@@ -160,10 +160,33 @@ hipError_t launch_fused_freq(gabor_plan p, int i, const float* d_image, int64_t 
     sa.out_scale = fl.out_scale;
     sa.tap_scale[0] = fl.tap_scale[0];
     sa.tap_scale[1] = fl.tap_scale[1];
+    if (fused_on_ws(p, i)) return launch_ws(p->fused_op, sa, fl.q, s);
     return launch_stream(p->fused_op, sa, fl.q, s);
 }
 
 }  // namespace
+
+namespace gabor {
+
+std::vector<BatchFreq> batch_freq_table(const gabor_plan_s* p)
+{
+    std::vector<BatchFreq> freqs(p->O);
+    for (int f = 0; f < p->O; ++f) {
+        const FreqLaunch& fl = p->launches[f];
+        BatchFreq& bf = freqs[f];
+        bf.R = p->freqs[f].R;
+        bf.seg_rows = fl.seg_rows;
+        bf.in_scale = fl.in_scale;
+        bf.mid_scale = fl.mid_scale;
+        bf.out_scale = fl.out_scale;
+        bf.tap_scale[0] = fl.tap_scale[0];
+        bf.tap_scale[1] = fl.tap_scale[1];
+        bf.q = fl.q;
+    }
+    return freqs;
+}
+
+}  // namespace gabor
 
 extern "C" const char* gabor_status_string(gabor_status s)
 {
@@ -217,6 +240,13 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
     p->N = n_orient;
     p->boundary = boundary;
     p->precision = precision;
+    // LIBGABOR_KERNEL=stream keeps every fused frequency on the four-wave
+    // streaming kernel (comparison and testing); the default runs the
+    // wave-specialised kernel wherever its quarter is built.
+    {
+        const char* k_env = std::getenv("LIBGABOR_KERNEL");
+        p->use_ws = !(k_env && std::strcmp(k_env, "stream") == 0);
+    }
     switch (precision) {
         case GABOR_PREC_FP32: p->fused_op = FUSED_F32; break;
         case GABOR_PREC_BF16_SPLIT: p->fused_op = FUSED_BF16X3; break;
@@ -727,7 +757,9 @@ extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int
         const FreqLaunch& fl = p->launches[i];
         hipStream_t ls = (j == 0 || n_aux == 0) ? stream : p->aux[(j - 1) % n_aux];
         if (fl.fused) {
-            LaunchTimer tm(p, ls, std::string(kFusedNames[p->fused_op]) + "_r" + std::to_string(p->freqs[i].R),
+            LaunchTimer tm(p, ls,
+                           std::string(fused_on_ws(p, i) ? kWsNames[p->fused_op] : kFusedNames[p->fused_op]) +
+                               "_r" + std::to_string(p->freqs[i].R),
                            fl.macs, fl.bytes);
             if (launch_fused_freq(p, i, d_image, row_stride_elems, d_out, fl.seg_rows, ls) != hipSuccess)
                 return GABOR_ERR_DEVICE;

@@ -22,6 +22,7 @@ struct FreqLaunch {
     int64_t bytes;    // algorithmic bytes of the launch
 };
 const char* const kFusedNames[5] = {"stream_f32", "stream_bf16", "stream_bf16x3", "stream_f16", "stream_f16x3"};
+const char* const kWsNames[5] = {"ws_f32", "ws_bf16", "ws_bf16x3", "ws_f16", "ws_f16x3"};
 enum { ALGO_AUTO = 0, ALGO_TWOPASS = 1 };
 }  // namespace gabor
 
@@ -55,6 +56,7 @@ struct gabor_plan_s {
     float2* d_iJ = nullptr;
     float2* d_iscr = nullptr;
     int fused_op = FUSED_F32;
+    bool use_ws = true;                    // wave-specialised kernel where built
     int32_t n_planes = 0;
     int32_t n_row_passes = 0, n_col_passes = 0;
     int64_t row_macs = 0, col_macs = 0;
@@ -77,6 +79,14 @@ struct gabor_plan_s {
 };
 
 namespace gabor {
+// Fused frequency i of the plan runs on the wave-specialised kernel.
+inline bool fused_on_ws(const gabor_plan_s* p, int i)
+{
+    return p->launches[i].fused && p->use_ws && ws_supported(p->fused_op, p->launches[i].q);
+}
+// The plan's frequency table as the batch kernels read it (R, segment rows,
+// scales, quarter per frequency).
+std::vector<BatchFreq> batch_freq_table(const gabor_plan_s* p);
 // Adjoint of the bank (gabor_plan.cpp): which kernels a plan's adjoint runs
 // (mfma: the matrix-core kernels) and the workspace bytes they need; then
 // the launches with a caller-provided workspace of at least that size.
