@@ -321,8 +321,10 @@ gabor_status lsdft_work(int32_t height, int32_t width, int32_t m_y, int32_t m_x,
  * segment height per fused frequency on the caller's image and output
  * buffers (d_out is overwritten) and keeps the fastest median of `reps`
  * timed launches; it then times whole applies with every height scaled by
- * 1, 2 and 4 (the frequencies run concurrently) and keeps the fastest.  It
- * synchronises hip_stream.  get/set copy the chosen heights
+ * 1, 2 and 4 (the frequencies run concurrently), keeps the fastest, and
+ * refines it by coordinate descent on the whole apply (each frequency's
+ * height retimed with the others fixed, two passes).  It synchronises
+ * hip_stream.  get/set copy the chosen heights
  * (n = number of frequencies; 0 for frequencies on the two-pass kernels) so
  * that a caller can cache them; set rejects heights below the image height
  * that are not positive multiples of 32, and replaces every height of at

@@ -915,17 +915,44 @@ extern "C" gabor_status gabor_bank_apply_adjoint(gabor_plan p, const void* d_gra
     return adjoint_run(p, mfma, ws, d_grad_out, d_grad_image, grad_row_stride_elems, (hipStream_t)hip_stream, true);
 }
 
-// Segment heights the tuner tries for one fused launch: multiples of 16 up
-// to the image height.
-static std::vector<int> seg_candidates(int H, int q)
+// Segment heights the tuner tries for one fused launch, up to the image
+// height: multiples of 32 for the four-wave kernel, of 16 for the
+// wave-specialised one (which also tries finer steps).
+static std::vector<int> seg_candidates(int H, int q, bool ws)
 {
     const int hmax = (H + 15) / 16 * 16;
     std::vector<int> c;
-    for (int v : {64, 128, 192, 256, 384, 512, 16 * q, 32 * q}) {
-        const int s = std::min(v, hmax);
-        if (s >= 16 && std::find(c.begin(), c.end(), s) == c.end()) c.push_back(s);
+    std::vector<int> v = {64, 128, 192, 256, 384, 512, 16 * q, 32 * q};
+    if (ws) v.insert(v.end(), {96, 160, 224, 320, 448, 640, 768, hmax});
+    for (int x : v) {
+        const int s = std::min(x, hmax);
+        if (s >= 16 && (ws || s % 32 == 0 || s == hmax) && std::find(c.begin(), c.end(), s) == c.end())
+            c.push_back(s);
     }
+    std::sort(c.begin(), c.end());
     return c;
+}
+
+// Median of reps timed applies (after one untimed one), in ms; sets *rc on
+// a device error.
+static double time_apply(gabor_plan p, const float* d_image, int64_t row_stride_elems, void* d_out, void* hip_stream,
+                         int reps, hipEvent_t a, hipEvent_t b, gabor_status* rc)
+{
+    hipStream_t stream = (hipStream_t)hip_stream;
+    std::vector<float> t;
+    for (int r = 0; r <= reps; ++r) {
+        float ms = 0.0f;
+        if (hipEventRecord(a, stream) != hipSuccess ||
+            gabor_bank_apply(p, d_image, row_stride_elems, d_out, hip_stream) != GABOR_OK ||
+            hipEventRecord(b, stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+            hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+            *rc = GABOR_ERR_DEVICE;
+            return 1e30;
+        }
+        if (r > 0) t.push_back(ms);
+    }
+    std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
+    return t[t.size() / 2];
 }
 
 extern "C" gabor_status gabor_bank_autotune(gabor_plan p, const float* d_image, int64_t row_stride_elems,
@@ -946,7 +973,7 @@ extern "C" gabor_status gabor_bank_autotune(gabor_plan p, const float* d_image, 
         if (!fl.fused) continue;
         double best = 1e30;
         int best_seg = fl.seg_rows;
-        for (int seg : seg_candidates(p->H, fl.q)) {
+        for (int seg : seg_candidates(p->H, fl.q, fused_on_ws(p, i))) {
             // one untimed launch, then the median of reps timed launches
             if (launch_fused_freq(p, i, d_image, row_stride_elems, d_out, seg, stream) != hipSuccess) { rc = GABOR_ERR_DEVICE; break; }
             std::vector<float> t;
@@ -981,27 +1008,36 @@ extern "C" gabor_status gabor_bank_autotune(gabor_plan p, const float* d_image, 
         for (int mult : {1, 2, 4}) {
             for (int i = 0; i < p->O; ++i)
                 if (p->launches[i].fused) p->launches[i].seg_rows = std::min(base_seg[i] * mult, hmax);
-            std::vector<float> t;
-            for (int r = 0; r <= reps && rc == GABOR_OK; ++r) {
-                float ms = 0.0f;
-                if (hipEventRecord(a, stream) != hipSuccess ||
-                    gabor_bank_apply(p, d_image, row_stride_elems, d_out, hip_stream) != GABOR_OK ||
-                    hipEventRecord(b, stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
-                    hipEventElapsedTime(&ms, a, b) != hipSuccess)
-                    rc = GABOR_ERR_DEVICE;
-                else if (r > 0)
-                    t.push_back(ms);                       // the first apply is untimed
-            }
+            const double t_med = time_apply(p, d_image, row_stride_elems, d_out, hip_stream, reps, a, b, &rc);
             if (rc != GABOR_OK) break;
-            std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
             // a scaled schedule must beat the per-launch optimum clearly
-            const double tm = t[t.size() / 2] * (mult == 1 ? 1.0 : 1.03);
+            const double tm = t_med * (mult == 1 ? 1.0 : 1.03);
             if (tm < best_t) {
                 best_t = tm;
                 for (int i = 0; i < p->O; ++i) best[i] = p->launches[i].seg_rows;
             }
         }
         for (int i = 0; i < p->O; ++i) p->launches[i].seg_rows = best[i];
+        // Coordinate descent on the whole apply: the frequencies share the
+        // device, so each one's height is retimed with the others fixed
+        // (two passes, heaviest frequency first).
+        if (rc == GABOR_OK) best_t = time_apply(p, d_image, row_stride_elems, d_out, hip_stream, reps, a, b, &rc);
+        for (int pass = 0; pass < 2 && rc == GABOR_OK; ++pass)
+            for (int i : p->order) {
+                if (!p->launches[i].fused || rc != GABOR_OK) continue;
+                int keep = p->launches[i].seg_rows;
+                for (int seg : seg_candidates(p->H, p->launches[i].q, fused_on_ws(p, i))) {
+                    if (seg == keep) continue;
+                    p->launches[i].seg_rows = seg;
+                    const double tm = time_apply(p, d_image, row_stride_elems, d_out, hip_stream, reps, a, b, &rc);
+                    if (rc != GABOR_OK) break;
+                    if (tm < 0.98 * best_t) {            // a clear gain only
+                        best_t = tm;
+                        keep = seg;
+                    }
+                }
+                p->launches[i].seg_rows = keep;
+            }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);

@@ -279,7 +279,8 @@ __device__ __forceinline__ void ws_body(const StreamArgs& a, const FusedJob& jb,
         }
         slab_store(pre_a, 0);
         lds_barrier();                                             // B2: slab 0 visible, sums read
-        // step t: fetch slab t + 2, J block t from slab t, stage slab t + 1
+        // step t: fetch slab t + 2, J block t from slab t (LDS buffer t & 1),
+        // stage slab t + 1 (into buffer (t + 1) & 1)
         auto hstep = [&](int t, float (&fet)[2 * PER_T], const float (&stg)[2 * PER_T], int buf) {
             if (t < nt - 1) {
                 slab_load(t + 2, fet);
@@ -395,11 +396,13 @@ __device__ __forceinline__ void ws_body(const StreamArgs& a, const FusedJob& jb,
             dc_b = make_float2(uni(cs * (vc * hc + vd * hd)), uni(cs * (vd * hc - vc * hd)));
         }
         lds_barrier();                                             // B2
+        // the same number of barriers as the row waves: steps in pairs
         for (int t = 0; t < nt; t += 2) {
-            if (t >= LEAD) col_pass(t - LEAD);
-            lds_barrier();
-            if (t + 1 >= LEAD && t + 1 < nt) col_pass(t + 1 - LEAD);
-            lds_barrier();
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                if (t + k >= LEAD && t + k < nt) col_pass(t + k - LEAD);
+                lds_barrier();
+            }
         }
     }
 }
