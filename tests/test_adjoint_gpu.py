@@ -201,6 +201,43 @@ def test_feature_layer_workload_sampled(gpu_lib):
         assert err <= 1e-5
 
 
+def test_feature_layer_finite_differences_64_pixels(gpu_lib):
+    """The layer workload's gradient check: one 512^2 image of the batch
+    (seed 5, zero boundary, 8 x 4 bank, sigma = pi / omega), L = mean |F|^2
+    over its outputs, central differences with h = 1e-3 at 64 seeded pixels.
+    Each difference sums |F|^2 in FP64 over the outputs within R of the pixel
+    (the others are bitwise equal in the two forwards and cancel); L is
+    quadratic, so the central difference has no truncation error and the
+    bar is set by the FP32 outputs' rounding."""
+    import torch
+    wl = workloads.bank_layer()
+    img = wl.images[0]
+    H, W = img.shape
+    g = loss_grad_gpu(gpu_lib, img, wl.omegas, wl.sigmas, wl.n_orient, None)
+    bank = gpu_lib.GaborBank(H, W, wl.omegas, wl.sigmas, wl.n_orient, None, 3.0, "zero", "fp32")
+    n = len(wl.omegas) * wl.n_orient * H * W
+    R = int(math.floor(3 * max(wl.sigmas) + 0.5))
+    h = 1e-3
+    xs, ys = workloads.sample_pixels(H, W, 64, 105)
+    base = torch.from_numpy(img).cuda()
+    fd = np.empty(len(xs))
+    for i, (x, y) in enumerate(zip(xs, ys)):
+        vals, steps = [], []
+        for sgn in (+1, -1):
+            # the step the FP32 image actually takes (f + h rounds)
+            v = np.float32(img[y, x] + np.float32(sgn * h))
+            steps.append(abs(float(v) - float(img[y, x])))
+            pert = base.clone()
+            pert[y, x] = float(v)
+            F = bank(pert)[:, :, max(0, y - R):y + R + 1, max(0, x - R):x + R + 1]
+            vals.append(float(torch.sum(torch.abs(F.to(torch.complex128)) ** 2)) / n)
+        fd[i] = (vals[0] - vals[1]) / (steps[0] + steps[1])
+    bank.close()
+    err = np.abs(fd - g[ys, xs]).max() / np.abs(g[ys, xs]).max()
+    print(f"layer 512^2 finite differences at 64 pixels: max err / peak {err:.2e}")
+    assert err <= 1e-4
+
+
 def draw(seed):
     """Shape, frequencies, radii, orientations and rule; the mirror rule's
     adjoint (transpose of the fold) is on the matrix cores, which take radii

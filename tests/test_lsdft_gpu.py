@@ -2,21 +2,19 @@
 through lsdft_apply against the FP64 oracle.
 
 Error measure (per bin): max over pixels of |F_gpu - F_ref| divided by max
-over pixels of |F_ref|.  Bars as for the bank: 1e-5 for FP32 and the
-float16 hi/lo split, 1e-3 for the bfloat16 hi/lo split, and 8 u max|f| /
-peak for single 16-bit products (|F| <= max|f| because the window weights
-sum to one on each axis).
+over pixels of |F_ref|, held to the bank's per-form bars (tests/bars.py;
+|F| <= max|f| here too, because the window weights sum to one on each
+axis).
 """
 import numpy as np
 import pytest
 
 import oracle
+from bars import channel_bars
 from paper_1704_05231_amd import workloads
 
 pytestmark = pytest.mark.gpu
 
-TOLS = {"fp32": 1e-5, "fp16_split": 1e-5, "bf16_split": 1e-3}
-UNIT = {"bf16": 2.0 ** -9, "fp16": 2.0 ** -12}
 PRECISIONS = ["fp32", "fp16_split", "bf16_split", "fp16", "bf16"]
 
 
@@ -39,10 +37,12 @@ def per_bin_err(got, ref, axis_pts):
     return num / np.maximum(den, 1e-300), den
 
 
-def tol(prec, img, peak):
-    if prec in TOLS:
-        return TOLS[prec]
-    return 8 * UNIT[prec] * np.abs(img).max() / peak
+def within(prec, img, err, peak):
+    """err (peak-relative, per bin) against the form's bars: the worst
+    ratio error / bar and the count of nearly cancelling bins."""
+    bar, nc = channel_bars(prec, float(np.abs(img).max()), peak)
+    ratio = err * peak / np.maximum(bar, 1e-300)
+    return ratio.max(), nc
 
 
 CASES = [
@@ -70,7 +70,9 @@ def test_lsdft_full_grid(gpu_lib, case, prec):
     assert np.all(np.isfinite(got)), "a bin plane was not written"
     err, peak = per_bin_err(got, ref, (2, 3))
     print(f"lsdft case {case} {H}x{W} {my}x{mx} {bnd} {prec}: max per-bin rel err {err.max():.3e}")
-    assert np.all(err <= tol(prec, img, peak))
+    worst, nc = within(prec, img, err, peak)
+    print(f"  worst err/bar {worst:.3f}, {nc} cancelling bins")
+    assert worst <= 1
 
 
 def test_lsdft_conjugate_bins_bitwise(gpu_lib):
@@ -103,7 +105,9 @@ def test_lsdft_largest_windows_sampled(gpu_lib, m):
         got = gpu_lsdft(gpu_lib, img, my, mx, 10.0, "mirror", prec)[:, :, ys, xs].transpose(2, 0, 1)
         err, peak = per_bin_err(got, ref, 0)
         print(f"lsdft {my}x{mx} {prec}: sampled max per-bin rel err {err.max():.3e}")
-        assert np.all(err <= tol(prec, img, peak))
+        worst, nc = within(prec, img, err, peak)
+        print(f"  worst err/bar {worst:.3f}, {nc} cancelling bins")
+        assert worst <= 1
 
 
 @pytest.fixture(scope="module")
@@ -124,7 +128,9 @@ def test_lsdft_512_sampled(gpu_lib, lsdft_512_ref, prec):
     g = got[:, :, ys, xs].transpose(2, 0, 1)
     err, peak = per_bin_err(g, ref, 0)
     print(f"lsdft-512 {prec}: sampled max per-bin rel err {err.max():.3e}")
-    assert np.all(err <= tol(prec, wl.image, peak))
+    worst, nc = within(prec, wl.image, err, peak)
+    print(f"  worst err/bar {worst:.3f}, {nc} cancelling bins")
+    assert worst <= 1
 
 
 def draw(seed):
@@ -149,4 +155,6 @@ def test_lsdft_random_configuration(gpu_lib, seed):
     assert np.all(np.isfinite(got)), "a bin plane was not written"
     err, peak = per_bin_err(got, ref, (2, 3))
     print(f"lsdft seed {seed} {H}x{W} {my}x{mx} sigma {sg:.2f} {bnd} {prec}: max per-bin rel err {err.max():.3e}")
-    assert np.all(err <= tol(prec, img, peak))
+    worst, nc = within(prec, img, err, peak)
+    print(f"  worst err/bar {worst:.3f}, {nc} cancelling bins")
+    assert worst <= 1
