@@ -12,7 +12,11 @@ form; the other arithmetic forms are reported beside it under ``forms``
 (bf16_split is the matrix-core form that meets the 1e-3 bar).  ``roofline``
 describes the launch that takes most of the FP32 step, timed live with HIP
 events that libgabor records on each launch's stream during the timed
-region, against the algorithmic work libgabor reports for that launch.
+region, against the algorithmic work libgabor reports for that launch (the
+four frequencies' launches run concurrently, so this time includes sharing
+the chip); beside it, ``step`` is the whole step's algorithmic work over
+``ms_per_step`` and ``isolated`` the same launch timed alone in a plan of its
+one frequency.
 ``cpu_baseline`` is the FP64 oracle (direct Eq. (1)) timed on the host on a
 bounded random sample of the same workload's outputs, which also gives the
 error of every form.
@@ -25,6 +29,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -37,16 +42,26 @@ sys.path.insert(0, ROOT)
 METRIC = "Gabor-bank complex outputs/s, 1024² 8θ×4ω bank: FP32 plain vs BF16-MFMA form"
 UNIT = "complex outputs/s"
 
-# MI355X published peaks
+# MI355X published peaks.  The FP32 vector figure is the unpacked rate (one
+# FMA per lane per cycle: 256 CUs x 64 lanes x 2 flops x 2.4 GHz): libgabor is
+# built without packed FP32 arithmetic, so the 157.3 TFLOP/s packed figure is
+# out of its reach.
 PEAK_HBM_GBS = 8000.0
-PEAK_TFLOPS = {"fp32_mfma": 157.3, "fp32_vector": 157.3, "bf16_mfma": 2500.0, "fp16_mfma": 2500.0}
+PEAK_TFLOPS = {"fp32_mfma": 157.3, "fp32_vector": 78.6, "bf16_mfma": 2500.0, "fp16_mfma": 2500.0}
 
 FORMS = ["fp32", "bf16_split", "fp16_split", "bf16", "fp16", "fp32_twopass"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = ["paper_1704_05231_amd/csrc/gabor_fused.hip", "paper_1704_05231_amd/csrc/gabor_fp32.hip"]
+KERNEL_SOURCES = ["paper_1704_05231_amd/csrc/gabor_ws.hip", "paper_1704_05231_amd/csrc/gabor_mfma.h",
+                  "paper_1704_05231_amd/csrc/gabor_fused.hip", "paper_1704_05231_amd/csrc/gabor_fp32.hip"]
 # HBM bytes of the box-window SDFT launch, from the same counters, keyed by its source
 SDFT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sdft-box-512sq-16x16.json")
 SDFT_SOURCES = ["paper_1704_05231_amd/csrc/gabor_sdft.hip"]
+# the same for the localized SDFT launch (k_lsdft) and the recursive smoother
+LSDFT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lsdft-512sq-16x16.json")
+LSDFT_SOURCES = ["paper_1704_05231_amd/csrc/gabor_fused.hip", "paper_1704_05231_amd/csrc/gabor_mfma.h",
+                 "paper_1704_05231_amd/csrc/gabor_lsdft.cpp"]
+IIR_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_iir-bank-1024sq-8x4-mirror.json")
+IIR_SOURCES = ["paper_1704_05231_amd/csrc/gabor_iir.hip"]
 
 
 def source_hash(sources=None) -> str:
@@ -87,7 +102,8 @@ def parse():
                          "(one single-frequency plan each, --steps launches, no concurrency) for each "
                          "listed form, and print their per-launch times (for counter runs)")
     ap.add_argument("--seg-rows", default="", metavar="S0,S1,..",
-                    help="with --isolate: segment heights per frequency (default: the plan's own)")
+                    help="segment heights per frequency for every form timed (no autotuning) or, with "
+                         "--isolate, for the isolated launches (default: autotuned / the plan's own)")
     return ap.parse_args()
 
 
@@ -95,7 +111,7 @@ def precision_of(form: str) -> str:
     return "fp32" if form == "fp32_twopass" else form
 
 
-def time_form(binding, wl, img_dev, form, steps, warmup, tune=True):
+def time_form(binding, wl, img_dev, form, steps, warmup, tune=True, seg_rows=None):
     import torch
     H, W = img_dev.shape
     if form == "fp32_twopass":
@@ -106,7 +122,9 @@ def time_form(binding, wl, img_dev, form, steps, warmup, tune=True):
     finally:
         os.environ.pop("LIBGABOR_ALGO", None)
     out = torch.empty((len(wl.omegas), wl.n_orient, H, W), dtype=torch.complex64, device="cuda")
-    tuning = bank.autotune(img_dev, out, reps=3) if tune else bank.tuning
+    if seg_rows:
+        bank.tuning = seg_rows
+    tuning = bank.autotune(img_dev, out, reps=3) if tune and not seg_rows else bank.tuning
     for _ in range(warmup):
         bank(img_dev, out)
     torch.cuda.synchronize()
@@ -161,6 +179,64 @@ def roofline_for(form, prof, traffic):
               "traffic_detail": t, "launch_ms": round(avg_s * 1e3, 5),
               "algorithmic_flops_per_launch": 2 * st["real_macs"],
               "algorithmic_bytes_per_launch": st["bytes"]})
+    return r
+
+
+def step_roofline(form, flops, nbytes, ms):
+    """Whole-step figure: the step's algorithmic flops and bytes (image read
+    once, every output written once) over the measured step time, against
+    the roof that binds it."""
+    kind, peak_c = ("alu", PEAK_TFLOPS["fp32_vector"]) if form == "fp32_twopass" else compute_peak(form, "")
+    tflops, gbs = flops / (ms * 1e-3) / 1e12, nbytes / (ms * 1e-3) / 1e9
+    fc, fm = tflops / peak_c, gbs / PEAK_HBM_GBS
+    if fc >= fm:
+        return {"bound": kind, "achieved": round(tflops, 3), "peak": peak_c, "unit": "TFLOP/s", "frac": round(fc, 4),
+                "hbm_frac": round(fm, 4), "flops_per_step": flops, "bytes_per_step": nbytes, "ms_per_step": ms}
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(fm, 4),
+            "compute_frac": round(fc, 4), "flops_per_step": flops, "bytes_per_step": nbytes, "ms_per_step": ms}
+
+
+def launch_radius(name: str) -> int:
+    """Radius in a launch's profile name (..._r48 -> 48)."""
+    return int(name.rsplit("_r", 1)[1])
+
+
+def isolated_launch(binding, wl, img_dev, form, name, tuning, steps, warmup):
+    """The launch `name` of the bank in a plan that holds only its frequency,
+    launched alone: its event-timed average with no other launch sharing the
+    chip, against the same per-launch algorithmic work."""
+    import torch
+    H, W = img_dev.shape
+    R = launch_radius(name)
+    i = [int(math.ceil(wl.radius_sigmas * s - 1e-9)) for s in wl.sigmas].index(R)
+    if form == "fp32_twopass":
+        os.environ["LIBGABOR_ALGO"] = "twopass"
+    try:
+        bank = binding.GaborBank(H, W, [wl.omegas[i]], [wl.sigmas[i]], wl.n_orient, None, wl.radius_sigmas,
+                                 wl.boundary, precision_of(form))
+    finally:
+        os.environ.pop("LIBGABOR_ALGO", None)
+    bank.tuning = [tuning[i]]
+    out = torch.empty((1, wl.n_orient, H, W), dtype=torch.complex64, device="cuda")
+    for _ in range(warmup):
+        bank(img_dev, out)
+    torch.cuda.synchronize()
+    bank.profile(True)
+    for _ in range(steps):
+        bank(img_dev, out)
+    torch.cuda.synchronize()
+    st = bank.profile_read()[name]
+    bank.profile(False)
+    bank.close()
+    avg_s = st["total_ms"] / st["launches"] * 1e-3
+    tflops, gbs = 2.0 * st["real_macs"] / avg_s / 1e12, st["bytes"] / avg_s / 1e9
+    kind, peak_c = compute_peak(form, name)
+    fc, fm = tflops / peak_c, gbs / PEAK_HBM_GBS
+    r = {"kernel": name, "launch_ms": round(avg_s * 1e3, 5), "segment_rows": tuning[i]}
+    if fc >= fm:
+        r.update({"bound": kind, "achieved": round(tflops, 3), "peak": peak_c, "unit": "TFLOP/s", "frac": round(fc, 4)})
+    else:
+        r.update({"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(fm, 4)})
     return r
 
 
@@ -238,14 +314,20 @@ def bench_lsdft(binding, workloads, steps, warmup):
     xs, ys = workloads.sample_pixels(H, W, 300, 31)
     ref = oracle.lsdft_points(wl.image, wl.my, wl.mx, wl.sigma, xs, ys, wl.boundary)
     peak = np.abs(ref).max(0)
+    # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters, per form
+    traffic = load_traffic(LSDFT_TRAFFIC_FILE, LSDFT_SOURCES) or {}
     res = {"workload": wl.name, "outputs_per_call": wl.my * wl.mx * H * W, "forms": {}}
     for form in ["fp32", "fp16_split", "bf16_split", "bf16", "fp16"]:
         ms = event_time(lambda: binding.lsdft(img, wl.my, wl.mx, wl.sigma, wl.boundary, form, out=out),
                         steps * 4, warmup)
         got = out.cpu().numpy()[:, :, ys, xs].transpose(2, 0, 1)
+        roof = hbm_roofline(nbytes, ms, "one launch per call")
+        t = traffic.get(form)
+        if t:
+            roof.update({"traffic": t["hbm_bytes"], "traffic_detail": t})
         res["forms"][form] = {"ms": round(ms, 5), "value": wl.my * wl.mx * H * W / (ms * 1e-3),
                               "max_rel_err_per_bin": float((np.abs(got - ref).max(0) / peak).max()),
-                              "roofline": hbm_roofline(nbytes, ms, "one launch per call")}
+                              "roofline": roof}
     res["unit"] = UNIT
     res["algorithmic_bytes"] = nbytes
     res["algorithmic_real_macs"] = macs
@@ -294,6 +376,18 @@ def bench_batch(binding, workloads, steps, warmup):
         batch = binding.GaborBatch(bank, imgs)
         ms = event_time(batch, steps, warmup)
         n_launch, n_tiles = batch.info
+        # the same batch captured once into a HIP graph and replayed
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            batch()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            batch()
+        torch.cuda.synchronize()
+        ms_graph = event_time(graph.replay, steps, warmup)
         worst = 0.0
         for i in (0, len(imgs) // 2, len(imgs) - 1):
             im = wl.images[i]
@@ -302,9 +396,12 @@ def bench_batch(binding, workloads, steps, warmup):
                                            wl.boundary)
             got = batch.outputs[i].cpu().numpy()[:, :, ys, xs].transpose(2, 0, 1)
             worst = max(worst, float((np.abs(got - ref).max(0) / np.abs(ref).max(0)).max()))
-        res["forms"][form] = {"ms": round(ms, 4), "value": n_out / (ms * 1e-3), "persistent_launches": n_launch,
-                              "tiles": n_tiles, "max_rel_err_sampled": worst,
-                              "roofline": hbm_roofline(nbytes, ms, "whole batch per call (several launches)")}
+        res["forms"][form] = {"ms": round(ms, 4), "value": n_out / (ms * 1e-3),
+                              "ms_graph_replay": round(ms_graph, 4), "value_graph_replay": n_out / (ms_graph * 1e-3),
+                              "persistent_launches": n_launch, "tiles": n_tiles, "max_rel_err_sampled": worst,
+                              "roofline": hbm_roofline(nbytes, ms_graph, "whole batch per graph replay "
+                                                                         "(one launch per operand size)")}
+        del graph
         batch.close()
         bank.close()
         del batch
@@ -379,8 +476,14 @@ def bench_iir(binding, workloads, steps, warmup):
     ser = 10 * np.log10((np.abs(ref) ** 2).sum(0) / (np.abs(got - ref) ** 2).sum(0))
     bank.close()
     n_out = len(wl.omegas) * wl.n_orient * H * W
+    roof = hbm_roofline(4 * H * W + 8 * n_out, ms, "whole apply (every launch of the recursive smoother)")
+    # HBM bytes of every launch of one apply, from the FETCH_SIZE / WRITE_SIZE counters
+    t = (load_traffic(IIR_TRAFFIC_FILE, IIR_SOURCES) or {}).get("apply")
+    if t:
+        roof.update({"traffic": t["hbm_bytes"], "traffic_detail": t})
     return {"workload": wl.name + " (recursive smoother)", "ms": round(ms, 4), "value": n_out / (ms * 1e-3),
-            "unit": UNIT, "ser_db_min": round(float(ser.min()), 2), "ser_db_max": round(float(ser.max()), 2)}
+            "unit": UNIT, "ser_db_min": round(float(ser.min()), 2), "ser_db_max": round(float(ser.max()), 2),
+            "roofline": roof}
 
 
 def isolate(binding, wl, img_dev, forms, steps, warmup, seg_rows):
@@ -392,8 +495,13 @@ def isolate(binding, wl, img_dev, forms, steps, warmup, seg_rows):
     res = {}
     for form in forms:
         for i, (om, sg) in enumerate(zip(wl.omegas, wl.sigmas)):
-            bank = binding.GaborBank(H, W, [om], [sg], wl.n_orient, None, wl.radius_sigmas, wl.boundary,
-                                     precision_of(form))
+            if form == "fp32_twopass":
+                os.environ["LIBGABOR_ALGO"] = "twopass"
+            try:
+                bank = binding.GaborBank(H, W, [om], [sg], wl.n_orient, None, wl.radius_sigmas, wl.boundary,
+                                         precision_of(form))
+            finally:
+                os.environ.pop("LIBGABOR_ALGO", None)
             if seg_rows:
                 bank.tuning = [seg_rows[i]]
             out = torch.empty((1, wl.n_orient, H, W), dtype=torch.complex64, device="cuda")
@@ -467,17 +575,17 @@ def main():
     H, W = img.shape
     n_out = len(wl.omegas) * wl.n_orient * H * W
     img_dev = torch.from_numpy(img).cuda()
+    seg = [int(v) for v in args.seg_rows.split(",") if v]
+    if seg and len(seg) != len(wl.omegas):
+        sys.exit("bench.py: --seg-rows needs one height per frequency")
     if args.isolate:
-        seg = [int(v) for v in args.seg_rows.split(",") if v]
-        if seg and len(seg) != len(wl.omegas):
-            sys.exit("bench.py: --seg-rows needs one height per frequency")
         isolate(binding, wl, img_dev, [f for f in args.isolate.split(",") if f], args.steps, args.warmup, seg)
         return
 
     forms, results = {}, {}
     for form in [f for f in args.forms.split(",") if f]:
         ms, prof, info, res, tuning = time_form(binding, wl, img_dev, form, args.steps, args.warmup,
-                                                not args.no_tune)
+                                                not args.no_tune, seg)
         results[form] = res
         forms[form] = {
             "value": n_out / (ms * 1e-3), "ms_per_step": round(ms, 5),
@@ -488,6 +596,12 @@ def main():
             "real_macs_per_step": info.real_macs,
             "segment_rows": tuning,
         }
+        forms[form]["roofline"]["step"] = step_roofline(form, 2 * info.real_macs, 4 * H * W + 8 * n_out,
+                                                        round(ms, 5))
+        if form in ("fp32", "bf16_split"):
+            forms[form]["roofline"]["isolated"] = isolated_launch(
+                binding, wl, img_dev, form, forms[form]["roofline"]["kernel"], tuning, args.steps, args.warmup)
+        print(f"bench.py: {form} done", file=sys.stderr, flush=True)
 
     cpu = None
     if forms and not args.no_cpu_baseline:
