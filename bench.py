@@ -421,9 +421,12 @@ def bench_layer(binding, workloads, steps, warmup):
     layer = GaborLayer(H, W, wl.omegas, wl.sigmas, wl.n_orient)
 
     def step():
+        # mean |F|^2 over all B x O x N x H x W outputs, as the squared
+        # 2-norm of the interleaved (re, im) view over the output count: one
+        # reading pass forward, one elementwise pass back
         x = x0.detach().requires_grad_(True)
         F = layer(x)
-        (F.real ** 2 + F.imag ** 2).mean().backward()
+        (torch.linalg.vector_norm(torch.view_as_real(F)) ** 2 / F.numel()).backward()
         return x.grad
 
     ms = event_time(step, steps, warmup)
@@ -435,9 +438,11 @@ def bench_layer(binding, workloads, steps, warmup):
     xs, ys = workloads.sample_pixels(H, W, 8, 55)
     ref = oracle.gabor_grad_points(wl.images[0], wl.omegas, wl.sigmas, wl.thetas_or_default, xs, ys) / B
     err = float(np.abs(g[0][ys, xs] - ref).max() / np.abs(ref).max())
-    # the matrix-core adjoint (fused frequencies) or the vector-ALU one
-    mfma = "adjoint_mfma_fp32" in prof
-    adj = prof.get("adjoint_mfma_fp32" if mfma else "adjoint_fp32")
+    # one batched adjoint call: the matrix-core adjoint (fused frequencies)
+    # or the vector-ALU one, named adjoint_*_x<B>
+    adj_name = next((k for k in prof if k.startswith("adjoint")), None)
+    adj = prof.get(adj_name) if adj_name else None
+    mfma = bool(adj_name) and adj_name.startswith("adjoint_mfma")
     adj_roof = None
     if adj:
         avg = adj["total_ms"] / adj["launches"]
@@ -446,12 +451,14 @@ def bench_layer(binding, workloads, steps, warmup):
         adj_roof = {"bound": "mfma" if mfma else "alu", "achieved": round(tf, 3), "peak": peak,
                     "unit": "TFLOP/s", "frac": round(tf / peak, 4), "traffic": None,
                     "launch_ms": round(avg, 5),
-                    "kernel": ("k_adj_stream, one launch per frequency" if mfma
-                               else "adjoint_fp32 (row + column pass)")}
+                    "kernel": (f"{adj_name}: k_adj_stream, one launch per frequency over the batch, and the sum"
+                               if mfma else f"{adj_name}: vector-ALU row + column passes")}
     layer.close()
     n_out = B * len(wl.omegas) * wl.n_orient * H * W
+    fwd = {k: round(v["total_ms"] / v["launches"], 4) for k, v in prof.items() if not k.startswith("adjoint")}
     return {"workload": wl.name, "ms_forward_backward": round(ms, 4), "value": n_out / (ms * 1e-3),
             "unit": "complex outputs/s (forward + backward)", "grad_max_rel_err_vs_oracle": err,
+            "forward_launch_ms": fwd, "adjoint_ms": round(adj["total_ms"] / adj["launches"], 4) if adj else None,
             "adjoint_roofline": adj_roof}
 
 

@@ -158,18 +158,67 @@ gabor_status gabor_bank_apply(gabor_plan plan, const float* d_image,
  *                     Under the mirror rule the sum runs over every position
  *                     p - t whose fold is q (the transpose of the fold).
  *
- * Plans whose frequencies all run in the fused kernel with R <= 56 use the
- * matrix cores (one partial plane per job, summed in job order); other zero
- * boundary plans use the vector-ALU kernels.  Mirror plans need the former
- * (and at most 32 frequencies), else GABOR_ERR_UNSUPPORTED.  The arithmetic
- * is FP32 whatever the plan's precision, and the result is deterministic.
- * The first call on a plan allocates its adjoint workspace (the partial
- * planes, of (H + 2R) x (W + 2R) pixels under the mirror rule; or one
- * complex plane per horizontal pass), which the plan keeps until destroyed;
- * later calls allocate nothing.
+ * Each frequency that runs in the fused kernel with R <= 56 takes the
+ * matrix cores (one partial plane per horizontal result); every other
+ * frequency takes the vector-ALU kernels (one partial plane).  The planes
+ * cover the image (zero boundary) or the image extended by the frequency's R
+ * (mirror rule), and a last launch sums them in a fixed order, folding the
+ * extended positions under the mirror rule.  A zero-boundary plan with no
+ * matrix-core frequency writes dL/df straight from the vector kernels.
+ * Mirror plans of more than 32 frequencies and recursive-smoother plans
+ * return GABOR_ERR_UNSUPPORTED.  The arithmetic is FP32 whatever the plan's
+ * precision, and the result is deterministic.  The first call on a plan
+ * allocates its adjoint workspace (4 bytes per partial-plane pixel, plus 8
+ * bytes per pixel of (W + 2R) wide rows per horizontal result of a
+ * vector-ALU frequency; or 8 bytes per pixel per horizontal result when the
+ * vector kernels write dL/df straight), which the plan keeps until
+ * destroyed; later calls allocate nothing.
  */
 gabor_status gabor_bank_apply_adjoint(gabor_plan plan, const void* d_grad_out, float* d_grad_image,
                                       int64_t grad_row_stride_elems, void* hip_stream);
+
+/*
+ * gabor_bank_apply_batched -- gabor_bank_apply over n_images images of the
+ * plan's size (Eq. (1) per image), in one launch per frequency when every
+ * frequency runs in the wave-specialised fused kernel (else one
+ * gabor_bank_apply per image, in order, on the stream).
+ *
+ *   d_images            device FP32; image b starts at d_images + b *
+ *                       image_stride_elems (>= (H - 1) * row_stride_elems + W
+ *                       when n_images > 1), rows row_stride_elems apart.
+ *   d_out               device complex64 [n_images][O][N][H][W], fully
+ *                       overwritten.
+ *
+ * n_images = 0 does nothing.  Results are bit-identical to gabor_bank_apply
+ * on each image.  Nothing is allocated; the plan serves one stream at a
+ * time.  Profiling names these launches <kernel>_r<R>_x<n_images>.
+ */
+gabor_status gabor_bank_apply_batched(gabor_plan plan, const float* d_images, int32_t n_images,
+                                      int64_t image_stride_elems, int64_t row_stride_elems, void* d_out,
+                                      void* hip_stream);
+
+/*
+ * gabor_bank_apply_adjoint_batched -- gabor_bank_apply_adjoint over
+ * n_images images (the adjoint of gabor_bank_apply_batched).
+ *
+ *   d_grad_out          device complex64 [n_images][O][N][H][W].
+ *   d_grad_images       device FP32; image b's gradient starts at
+ *                       d_grad_images + b * grad_image_stride_elems (>= (H - 1)
+ *                       * grad_row_stride_elems + W when n_images > 1), rows
+ *                       grad_row_stride_elems apart; fully overwritten.
+ *
+ * The matrix-core frequencies take every image of a group in one launch, and
+ * one launch sums each group; groups hold as many images as fit a 1 GiB
+ * workspace (at least one).  The plan's adjoint workspace grows to one
+ * group's size at the first call that needs it (after synchronising the
+ * stream when an older, smaller one is replaced), so a call that allocates
+ * cannot be captured in a HIP graph; once grown, calls allocate nothing.
+ * Results are bit-identical to gabor_bank_apply_adjoint on each image.
+ * n_images = 0 does nothing.
+ */
+gabor_status gabor_bank_apply_adjoint_batched(gabor_plan plan, const void* d_grad_out, int32_t n_images,
+                                              float* d_grad_images, int64_t grad_image_stride_elems,
+                                              int64_t grad_row_stride_elems, void* hip_stream);
 
 /*
  * gabor_bank_apply_adjoint_noalloc -- gabor_bank_apply_adjoint for callers
@@ -178,11 +227,12 @@ gabor_status gabor_bank_apply_adjoint(gabor_plan plan, const void* d_grad_out, f
  * kernels and bit-identical results, but the workspace comes from a fixed
  * array of 64 MiB that the library holds on each GPU it runs on (until the
  * process ends) instead of memory the plan allocates; the call allocates
- * nothing.  The workspace a plan needs is 4 bytes per partial-plane pixel
- * on the matrix cores (jobs x (H + 2R) x (W + 2R) summed over the
- * frequencies, R = 0 under the zero boundary) or 8 bytes per pixel per
- * horizontal pass on the vector ALUs; a plan that needs more than 64 MiB
- * returns GABOR_ERR_UNSUPPORTED before anything is enqueued.  Every call on
+ * nothing.  The workspace a plan needs is that of gabor_bank_apply_adjoint
+ * (4 bytes per partial-plane pixel: horizontal results x (H + 2R) x (W + 2R)
+ * summed over the matrix-core frequencies, one such plane per vector-ALU
+ * frequency, R = 0 under the zero boundary, plus the vector kernels'
+ * complex rows); a plan that needs more than 64 MiB returns
+ * GABOR_ERR_UNSUPPORTED before anything is enqueued.  Every call on
  * one GPU shares that GPU's array, so calls whose executions overlap on one
  * GPU (different streams, or different host threads) race and give wrong
  * results; serialise them.  The first call on a device looks up the array's

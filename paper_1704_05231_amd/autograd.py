@@ -1,11 +1,10 @@
 """Differentiable Gabor feature layer: libgabor's forward bank and its
 hand-written adjoint behind ``torch.autograd.Function``.
 
-The forward is ``gabor_bank_apply``; the backward is
-``gabor_bank_apply_adjoint``, which maps dL/dF (complex64, PyTorch's
-convention dL/dRe F + i dL/dIm F) to dL/df.  Both run in libgabor's HIP
-kernels; nothing here computes.  The mirror rule's adjoint needs every
-frequency in the fused kernel (R <= 56); the zero boundary has no limit.
+The forward is ``gabor_bank_apply`` (``gabor_bank_apply_batched`` for a
+batch); the backward is ``gabor_bank_apply_adjoint`` (``..._batched``),
+which maps dL/dF (complex64, PyTorch's convention dL/dRe F + i dL/dIm F) to
+dL/df.  Both run in libgabor's HIP kernels; nothing here computes.
 """
 from __future__ import annotations
 
@@ -29,30 +28,18 @@ class GaborBankFunction(torch.autograd.Function):
 
 
 class GaborBatchFunction(torch.autograd.Function):
-    """F[b] = bank(f[b]) for a float32 [B, H, W] batch, every image written
-    straight into its slice of one complex64 [B, O, N, H, W] output; the
-    backward writes each image's dL/df into its slice of one [B, H, W]
-    gradient."""
+    """F[b] = bank(f[b]) for a float32 [B, H, W] batch into one complex64
+    [B, O, N, H, W] output (one batched forward call); the backward is one
+    batched adjoint call into a [B, H, W] gradient."""
 
     @staticmethod
     def forward(ctx, x, bank):
         ctx.bank = bank
-        x = x.contiguous()
-        out = torch.empty((x.shape[0], bank.n_freq, bank.n_orient, bank.height, bank.width),
-                          dtype=torch.complex64, device=x.device)
-        for b in range(x.shape[0]):
-            bank(x[b], out[b])
-        return out
+        return bank.apply_batched(x.contiguous())
 
     @staticmethod
     def backward(ctx, grad_out):
-        grad_out = grad_out.contiguous()
-        bank = ctx.bank
-        grad = torch.empty((grad_out.shape[0], bank.height, bank.width), dtype=torch.float32,
-                           device=grad_out.device)
-        for b in range(grad_out.shape[0]):
-            bank.adjoint(grad_out[b], grad[b])
-        return grad, None
+        return ctx.bank.adjoint_batched(grad_out.contiguous()), None
 
 
 class GaborLayer(torch.nn.Module):

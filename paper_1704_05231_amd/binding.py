@@ -30,7 +30,7 @@ PRECISION = {"fp32": 0, "bf16_split": 1, "fp16_split": 2, "bf16": 3, "fp16": 4}
 
 # Every symbol include/libgabor.h declares; the CPU tests check the exports.
 EXPORTS = ["gabor_status_string", "gabor_bank_plan", "gabor_bank_plan_iir", "gabor_bank_apply", "gabor_bank_apply_adjoint",
-           "gabor_bank_apply_adjoint_noalloc",
+           "gabor_bank_apply_adjoint_noalloc", "gabor_bank_apply_batched", "gabor_bank_apply_adjoint_batched",
            "gabor_bank_destroy", "gabor_batch_create", "gabor_batch_apply", "gabor_batch_info",
            "gabor_batch_destroy", "gabor_bank_autotune", "gabor_bank_get_tuning", "gabor_bank_set_tuning",
            "lsdft_apply", "lsdft_work", "sdft_box_apply", "gabor_bank_plan_info", "gabor_profile_enable",
@@ -85,6 +85,10 @@ def load():
     lib.gabor_bank_apply_adjoint.restype = ctypes.c_int
     lib.gabor_bank_apply_adjoint_noalloc.argtypes = [P, P, P, i64, P]
     lib.gabor_bank_apply_adjoint_noalloc.restype = ctypes.c_int
+    lib.gabor_bank_apply_batched.argtypes = [P, P, i32, i64, i64, P, P]
+    lib.gabor_bank_apply_batched.restype = ctypes.c_int
+    lib.gabor_bank_apply_adjoint_batched.argtypes = [P, P, i32, P, i64, i64, P]
+    lib.gabor_bank_apply_adjoint_batched.restype = ctypes.c_int
     lib.gabor_bank_destroy.argtypes = [P]
     lib.gabor_bank_destroy.restype = ctypes.c_int
     lib.gabor_bank_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
@@ -192,6 +196,21 @@ def gabor_bank_apply_adjoint_noalloc(plan, d_grad_out: int, d_grad_image: int, g
     st = load().gabor_bank_apply_adjoint_noalloc(plan, ctypes.c_void_p(d_grad_out), ctypes.c_void_p(d_grad_image),
                                                  int(grad_row_stride_elems), _stream(stream))
     _check(st, "gabor_bank_apply_adjoint_noalloc")
+
+
+def gabor_bank_apply_batched(plan, d_images: int, n_images: int, image_stride_elems: int, row_stride_elems: int,
+                             d_out: int, stream=None):
+    st = load().gabor_bank_apply_batched(plan, ctypes.c_void_p(d_images), int(n_images), int(image_stride_elems),
+                                         int(row_stride_elems), ctypes.c_void_p(d_out), _stream(stream))
+    _check(st, "gabor_bank_apply_batched")
+
+
+def gabor_bank_apply_adjoint_batched(plan, d_grad_out: int, n_images: int, d_grad_images: int,
+                                     grad_image_stride_elems: int, grad_row_stride_elems: int, stream=None):
+    st = load().gabor_bank_apply_adjoint_batched(plan, ctypes.c_void_p(d_grad_out), int(n_images),
+                                                 ctypes.c_void_p(d_grad_images), int(grad_image_stride_elems),
+                                                 int(grad_row_stride_elems), _stream(stream))
+    _check(st, "gabor_bank_apply_adjoint_batched")
 
 
 def gabor_bank_destroy(plan):
@@ -389,6 +408,40 @@ class GaborBank:
         gabor_bank_apply_adjoint(self._plan, grad_out.data_ptr(), grad_img.data_ptr(), grad_img.stride(0),
                                  stream)
         return grad_img
+
+    def apply_batched(self, imgs, out=None, stream=None):
+        """Every image of a float32 [B, H, W] GPU tensor (rows contiguous)
+        into complex64 [B, O, N, H, W]: one launch per frequency."""
+        import torch
+        if imgs.dtype != torch.float32 or imgs.dim() != 3 or not imgs.is_cuda:
+            raise ValueError("images must be a 3-D float32 GPU tensor")
+        if tuple(imgs.shape[1:]) != (self.height, self.width) or imgs.stride(2) != 1:
+            raise ValueError("image shape does not match the plan or rows are not contiguous")
+        B = imgs.shape[0]
+        shape = (B, self.n_freq, self.n_orient, self.height, self.width)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.complex64, device=imgs.device)
+        elif out.dtype != torch.complex64 or not out.is_contiguous() or tuple(out.shape) != shape:
+            raise ValueError("out must be a contiguous complex64 [B, O, N, H, W] tensor")
+        gabor_bank_apply_batched(self._plan, imgs.data_ptr(), B, imgs.stride(0), imgs.stride(1), out.data_ptr(),
+                                 stream)
+        return out
+
+    def adjoint_batched(self, grad_out, grad_imgs=None, stream=None):
+        """dL/df (float32 [B, H, W]) from dL/dF (complex64 [B, O, N, H, W])."""
+        import torch
+        B = grad_out.shape[0] if grad_out.dim() == 5 else -1
+        if (grad_out.dtype != torch.complex64 or not grad_out.is_contiguous() or not grad_out.is_cuda
+                or tuple(grad_out.shape) != (B, self.n_freq, self.n_orient, self.height, self.width)):
+            raise ValueError("grad_out must be a contiguous complex64 [B, O, N, H, W] GPU tensor")
+        if grad_imgs is None:
+            grad_imgs = torch.empty((B, self.height, self.width), dtype=torch.float32, device=grad_out.device)
+        elif (grad_imgs.dtype != torch.float32 or grad_imgs.dim() != 3 or grad_imgs.stride(2) != 1
+              or tuple(grad_imgs.shape) != (B, self.height, self.width)):
+            raise ValueError("grad_imgs must be a float32 [B, H, W] tensor with contiguous rows")
+        gabor_bank_apply_adjoint_batched(self._plan, grad_out.data_ptr(), B, grad_imgs.data_ptr(),
+                                         grad_imgs.stride(0), grad_imgs.stride(1), stream)
+        return grad_imgs
 
     def autotune(self, img, out=None, reps: int = 5, stream=None) -> list[int]:
         """Time the candidate schedules on img (and out, overwritten); keep the fastest."""

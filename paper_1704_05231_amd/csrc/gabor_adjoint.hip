@@ -1,6 +1,6 @@
-// Adjoint of the Gabor bank with the zero boundary: the gradient of a real
-// loss with respect to the image, given its gradient with respect to every
-// output channel.
+// Adjoint of the Gabor bank on the vector ALU: the gradient of a real loss
+// with respect to the image, given its gradient with respect to every output
+// channel.
 //
 // Eq. (1) is F_c = f * K_c with K_c(t) = S(t_x) S(t_y) exp(i w (t_x cos(theta)
 // + t_y sin(theta))).  For a real loss and G_c = dL/dRe F_c + i dL/dIm F_c,
@@ -18,7 +18,13 @@
 //   alone:  A = Re G_a, B = -Im G_a, C = Im G_a, D = Re G_a,
 //   pair:   A = Re(G_a + G_b), B = Im(G_b - G_a), C = Im(G_a + G_b), D = Re(G_a - G_b).
 // Vertical pass (one per horizontal result): Re(J * k_y) = Re J * c - Im J * d,
-// accumulated over every job of the bank in registers and written once.
+// accumulated over every job of the launch in registers and written once.
+//
+// Both passes can run on a grid extended by `off` on every side (J planes
+// [H][W + 2 off], output [H + 2 off][W + 2 off], pixel (y, x) at image
+// position (y - off, x - off), G zero outside the image): with off = R this
+// is the adjoint on the mirror rule's extended image, whose positions the
+// caller then folds back onto the pixels they mirror.
 #include "gabor_internal.h"
 
 namespace gabor {
@@ -29,9 +35,10 @@ constexpr int kAdjRowThreads = 256;
 constexpr int kAdjColTX = 32, kAdjColTY = 64, kAdjColP = 8;
 
 __global__ __launch_bounds__(kAdjRowThreads) void k_adj_row(
-    const float2* __restrict__ G, int H, int W, const AdjJob* __restrict__ jobs,
+    const float2* __restrict__ G, int H, int W, int off, const AdjJob* __restrict__ jobs,
     const float* __restrict__ taps, float2* __restrict__ J)
 {
+    const int Wo = W + 2 * off;
     constexpr int P = kAdjRowP;
     extern __shared__ float4 adj_row_lds4[];
     const AdjJob jb = jobs[blockIdx.z];
@@ -47,7 +54,7 @@ __global__ __launch_bounds__(kAdjRowThreads) void k_adj_row(
     const float2* ga = G + (int64_t)jb.out_a * plane + (int64_t)y * W;
     const float2* gb = jb.out_b >= 0 ? G + (int64_t)jb.out_b * plane + (int64_t)y * W : nullptr;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int xx = x0 - R + i;
+        const int xx = x0 - off - R + i;
         float2 a = make_float2(0.f, 0.f), b = make_float2(0.f, 0.f);
         if (xx >= 0 && xx < W) {
             a = ga[xx];
@@ -116,16 +123,16 @@ __global__ __launch_bounds__(kAdjRowThreads) void k_adj_row(
             }
         }
     }
-    float2* dst = J + (int64_t)blockIdx.z * plane + (int64_t)y * W;
+    float2* dst = J + (int64_t)blockIdx.z * H * Wo + (int64_t)y * Wo;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const int x = x0 + base + p;
-        if (x < W) dst[x] = make_float2(re[p], im[p]);
+        if (x < Wo) dst[x] = make_float2(re[p], im[p]);
     }
 }
 
 __global__ __launch_bounds__(kAdjColTX * (kAdjColTY / kAdjColP)) void k_adj_col(
-    const float2* __restrict__ J, int H, int W, const AdjJob* __restrict__ jobs, int n_jobs,
+    const float2* __restrict__ J, int H, int W, int off, const AdjJob* __restrict__ jobs, int n_jobs,
     const float* __restrict__ taps, float* __restrict__ grad, int64_t grad_stride)
 {
     constexpr int TX = kAdjColTX, TY = kAdjColTY, P = kAdjColP;
@@ -134,7 +141,8 @@ __global__ __launch_bounds__(kAdjColTX * (kAdjColTY / kAdjColP)) void k_adj_col(
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
     const int x = x0 + tx;
-    const int64_t plane = (int64_t)H * W;
+    const int Ho = H + 2 * off, Wo = W + 2 * off;
+    const int64_t plane = (int64_t)H * Wo;
     float acc[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) acc[p] = 0.f;
@@ -146,8 +154,8 @@ __global__ __launch_bounds__(kAdjColTX * (kAdjColTY / kAdjColP)) void k_adj_col(
         __syncthreads();                                     // previous job's reads are done
         for (int i = threadIdx.x; i < rows * TX; i += blockDim.x) {
             const int r = i / TX, cx = i % TX;
-            const int yy = y0 - R + r, xx = x0 + cx;
-            tile[i] = (yy >= 0 && yy < H && xx < W) ? src[(int64_t)yy * W + xx] : make_float2(0.f, 0.f);
+            const int yy = y0 - off - R + r, xx = x0 + cx;
+            tile[i] = (yy >= 0 && yy < H && xx < Wo) ? src[(int64_t)yy * Wo + xx] : make_float2(0.f, 0.f);
         }
         __syncthreads();
         const float* tc = taps + jb.tap_off + 2 * Kp;        // col c
@@ -181,11 +189,11 @@ __global__ __launch_bounds__(kAdjColTX * (kAdjColTY / kAdjColP)) void k_adj_col(
             }
         }
     }
-    if (x < W) {
+    if (x < Wo) {
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const int y = y0 + ty * P + p;
-            if (y < H) grad[(int64_t)y * grad_stride + x] = acc[p];
+            if (y < Ho) grad[(int64_t)y * grad_stride + x] = acc[p];
         }
     }
 }
@@ -195,11 +203,13 @@ __global__ __launch_bounds__(kAdjColTX * (kAdjColTY / kAdjColP)) void k_adj_col(
 size_t adj_row_lds_bytes(int max_kp) { return 4 * sizeof(float) * (size_t)(kAdjRowThreads * kAdjRowP + max_kp); }
 size_t adj_col_lds_bytes(int max_kp) { return sizeof(float2) * (size_t)(kAdjColTY + max_kp) * kAdjColTX; }
 
-hipError_t launch_adjoint(const float2* d_G, int H, int W, const AdjJob* d_jobs, int n_jobs, int max_kp,
-                          const float* d_taps, float2* d_J, float* d_grad, int64_t grad_stride,
+hipError_t launch_adjoint(const float2* d_G, int H, int W, int off, const AdjJob* d_jobs, int n_jobs,
+                          int max_kp, const float* d_taps, float2* d_J, float* d_grad, int64_t grad_stride,
                           hipStream_t stream)
 {
-    if (n_jobs <= 0 || n_jobs > 65535 || H > 65535) return hipErrorInvalidValue;
+    if (n_jobs <= 0 || n_jobs > 65535 || H > 65535 || off < 0) return hipErrorInvalidValue;
+    const int Ho = H + 2 * off, Wo = W + 2 * off;
+    if (grad_stride < Wo) return hipErrorInvalidValue;
     const size_t row_lds = adj_row_lds_bytes(max_kp), col_lds = adj_col_lds_bytes(max_kp);
     if (row_lds > 160 * 1024 || col_lds > 160 * 1024) return hipErrorInvalidValue;
     hipError_t e;
@@ -212,12 +222,12 @@ hipError_t launch_adjoint(const float2* d_G, int H, int W, const AdjJob* d_jobs,
                                  (int)col_lds)) != hipSuccess)
         return e;
     const int seg = kAdjRowThreads * kAdjRowP;
-    hipLaunchKernelGGL(k_adj_row, dim3((W + seg - 1) / seg, H, n_jobs), dim3(kAdjRowThreads), row_lds, stream,
-                       d_G, H, W, d_jobs, d_taps, d_J);
+    hipLaunchKernelGGL(k_adj_row, dim3((Wo + seg - 1) / seg, H, n_jobs), dim3(kAdjRowThreads), row_lds, stream,
+                       d_G, H, W, off, d_jobs, d_taps, d_J);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_col, dim3((W + kAdjColTX - 1) / kAdjColTX, (H + kAdjColTY - 1) / kAdjColTY),
+    hipLaunchKernelGGL(k_adj_col, dim3((Wo + kAdjColTX - 1) / kAdjColTX, (Ho + kAdjColTY - 1) / kAdjColTY),
                        dim3(kAdjColTX * (kAdjColTY / kAdjColP)), col_lds, stream,
-                       (const float2*)d_J, H, W, d_jobs, n_jobs, d_taps, d_grad, grad_stride);
+                       (const float2*)d_J, H, W, off, d_jobs, n_jobs, d_taps, d_grad, grad_stride);
     return hipGetLastError();
 }
 

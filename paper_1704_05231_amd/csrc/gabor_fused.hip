@@ -871,7 +871,15 @@ __device__ __forceinline__ void adj_job(const AdjStreamArgs& a, const FusedJob& 
 template <int Q>
 __global__ __launch_bounds__(kThreads) void k_adj_stream(AdjStreamArgs a)
 {
-    const int lid = xcd_local_id(blockIdx.x, gridDim.x);
+    int lid = xcd_local_id(blockIdx.x, gridDim.x);
+    if (a.n_images > 1) {
+        // strided batch: image-major workgroup ids
+        const int per = a.n_jobs * a.n_xs * a.n_ys;
+        const int b = lid / per;
+        lid -= b * per;
+        a.G += b * a.g_bstride;
+        a.part += b * a.part_bstride;
+    }
     const int job = lid % a.n_jobs, rest = lid / a.n_jobs;
     const int xs = rest % a.n_xs, ys = rest / a.n_xs;
     const int x0 = xs * kSX, yseg = ys * a.seg_rows;
@@ -883,11 +891,14 @@ __global__ __launch_bounds__(kThreads) void k_adj_stream(AdjStreamArgs a)
 }
 
 __global__ __launch_bounds__(256) void k_adj_sum(const float* __restrict__ part, int n, int H, int W,
-                                                 float* __restrict__ grad, int64_t stride)
+                                                 float* __restrict__ grad, int64_t stride, int64_t part_bstride,
+                                                 int64_t grad_bstride)
 {
     const int64_t npix = (int64_t)H * W;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= npix) return;
+    part += blockIdx.y * part_bstride;      // image of a batch
+    grad += blockIdx.y * grad_bstride;
     float s = 0.f;
     for (int j = 0; j < n; ++j) s += part[j * npix + i];
     const int64_t y = i / W, x = i - y * W;
@@ -910,6 +921,8 @@ __global__ __launch_bounds__(256) void k_adj_fold_sum(AdjFoldArgs a)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= (int64_t)a.H * a.W) return;
+    a.part += blockIdx.y * a.part_bstride;  // image of a batch
+    a.grad += blockIdx.y * a.grad_bstride;
     const int qy = (int)(i / a.W), qx = (int)(i - (int64_t)qy * a.W);
     float s = 0.f;
     for (int f = 0; f < a.n_freq; ++f) {
@@ -959,7 +972,8 @@ hipError_t launch_adj_q(const AdjStreamArgs& a, hipStream_t stream)
                                            (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_adj_stream<Q>, dim3(a.n_jobs * a.n_xs * a.n_ys), dim3(kThreads), lds, stream, a);
+    hipLaunchKernelGGL(k_adj_stream<Q>, dim3(a.n_jobs * a.n_xs * a.n_ys * (a.n_images > 1 ? a.n_images : 1)),
+                       dim3(kThreads), lds, stream, a);
     return hipGetLastError();
 }
 
@@ -1030,7 +1044,9 @@ hipError_t launch_adjoint_stream(const AdjStreamArgs& a, int Q, hipStream_t stre
         return hipErrorInvalidValue;
     if (a.Ho < a.H || a.Wo < a.W || a.off < 0 || a.n_xs * kSX < a.Wo || (int64_t)a.n_ys * a.seg_rows < a.Ho)
         return hipErrorInvalidValue;
-    if ((long long)a.n_jobs * a.n_xs * a.n_ys > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (a.n_images > 1 && (a.g_bstride < 0 || a.part_bstride < 0)) return hipErrorInvalidValue;
+    if ((long long)a.n_jobs * a.n_xs * a.n_ys * (a.n_images > 1 ? a.n_images : 1) > 0x7fffffffLL)
+        return hipErrorInvalidValue;
     return launch_adj_stream_q<4, 8, 12, 16, 20, 24, 28, 32>(a, Q, stream);
 }
 
@@ -1039,17 +1055,21 @@ hipError_t launch_adjoint_fold_sum(const AdjFoldArgs& a, hipStream_t stream)
     const int64_t npix = (int64_t)a.H * a.W;
     if (a.n_freq <= 0 || a.n_freq > kAdjFoldMaxFreq || npix <= 0 || (npix + 255) / 256 > 0x7fffffffLL)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_adj_fold_sum, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, stream, a);
+    const int nb = a.n_images > 1 ? a.n_images : 1;
+    if (nb > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_adj_fold_sum, dim3((unsigned)((npix + 255) / 256), nb), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint_sum(const float* part, int n, int H, int W, float* grad, int64_t grad_stride,
-                              hipStream_t stream)
+                              int n_images, int64_t part_bstride, int64_t grad_bstride, hipStream_t stream)
 {
     const int64_t npix = (int64_t)H * W;
     if (n <= 0 || npix <= 0 || (npix + 255) / 256 > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_adj_sum, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, stream, part, n, H, W, grad,
-                       grad_stride);
+    const int nb = n_images > 1 ? n_images : 1;
+    if (nb > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_adj_sum, dim3((unsigned)((npix + 255) / 256), nb), dim3(256), 0, stream, part, n, H, W,
+                       grad, grad_stride, part_bstride, grad_bstride);
     return hipGetLastError();
 }
 

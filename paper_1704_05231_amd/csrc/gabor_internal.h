@@ -70,6 +70,11 @@ struct StreamArgs {
     float mid_scale;           // J scale after the horizontal pass
     float out_scale;           // output scale after the vertical pass
     float tap_scale[2];        // horizontal, vertical tap scales
+    // Images of one strided batch (wave-specialised kernel only; 1 and 0
+    // elsewhere): image b reads img + b * img_bstride and writes
+    // out + b * out_bstride.
+    int32_t n_images;
+    int64_t img_bstride, out_bstride;
 };
 
 // Adjoint on the matrix cores: one launch per fused frequency (FP32), one
@@ -87,13 +92,18 @@ struct AdjStreamArgs {
     int32_t R, seg_rows, n_xs, n_ys, n_jobs;
     const FusedJob* jobs;      // this frequency's jobs
     const float* taps;         // reversed taps, fused-kernel layout [4][4Q + 16]
+    // strided batch: image b reads G + b * g_bstride, writes part + b * part_bstride
+    int32_t n_images;
+    int64_t g_bstride, part_bstride;
 };
 constexpr int kAdjStreamMaxQuarter = 32;   // R <= 56
 size_t adjoint_stream_lds_bytes(int Q);
 hipError_t launch_adjoint_stream(const AdjStreamArgs& a, int Q, hipStream_t stream);
-// zero boundary: dL/df[y][x] = sum over the n planes [H][W] of part, in plane order
+// zero boundary: dL/df[y][x] = sum over the n planes [H][W] of part, in plane
+// order; image b of a batch of n_images sums part + b * part_bstride into
+// grad + b * grad_bstride
 hipError_t launch_adjoint_sum(const float* part, int n, int H, int W, float* grad, int64_t grad_stride,
-                              hipStream_t stream);
+                              int n_images, int64_t part_bstride, int64_t grad_bstride, hipStream_t stream);
 // mirror rule: per frequency, planes [count][H + 2R][W + 2R] from element base
 struct AdjFoldFreq {
     int64_t base;
@@ -104,7 +114,8 @@ struct AdjFoldArgs {
     const float* part;
     float* grad;
     int64_t grad_stride;
-    int32_t H, W, n_freq, pad_;
+    int32_t H, W, n_freq, n_images;
+    int64_t part_bstride, grad_bstride;   // per image of a batch
     AdjFoldFreq f[kAdjFoldMaxFreq];
 };
 hipError_t launch_adjoint_fold_sum(const AdjFoldArgs& a, hipStream_t stream);
@@ -210,10 +221,13 @@ struct AdjJob {
 
 size_t adj_row_lds_bytes(int max_kp);
 size_t adj_col_lds_bytes(int max_kp);
-// Horizontal adjoint pass of every job into d_J ([n_jobs][H][W]), then the
-// vertical pass summed over the jobs into d_grad (gabor_adjoint.hip).
-hipError_t launch_adjoint(const float2* d_G, int H, int W, const AdjJob* d_jobs, int n_jobs, int max_kp,
-                          const float* d_taps, float2* d_J, float* d_grad, int64_t grad_stride,
+// Horizontal adjoint pass of every job into d_J ([n_jobs][H][Wo]), then the
+// vertical pass summed over the jobs into d_grad, an Ho x Wo grid whose
+// pixel (y, x) is image position (y - off, x - off) with Ho = H + 2 off and
+// Wo = W + 2 off (gabor_adjoint.hip).  off = 0 gives the zero boundary's
+// gradient itself; the mirror rule takes off = R and folds the grid.
+hipError_t launch_adjoint(const float2* d_G, int H, int W, int off, const AdjJob* d_jobs, int n_jobs,
+                          int max_kp, const float* d_taps, float2* d_J, float* d_grad, int64_t grad_stride,
                           hipStream_t stream);
 
 // Recursive-smoother variant (gabor_iir.hip): one recursion job runs a

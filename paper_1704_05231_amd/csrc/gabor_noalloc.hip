@@ -47,13 +47,12 @@ extern "C" gabor_status gabor_bank_apply_adjoint_noalloc(gabor_plan p, const voi
 {
     if (!p || !d_grad_out || !d_grad_image) return GABOR_ERR_INVALID_ARG;
     if (grad_row_stride_elems < p->W) return GABOR_ERR_INVALID_ARG;
-    bool mfma = false;
-    int64_t bytes = 0;
-    const gabor_status st = gabor::adjoint_workspace(p, &mfma, &bytes);
+    gabor::AdjLayout L;
+    const gabor_status st = gabor::adjoint_layout(p, &L);
     if (st != GABOR_OK) return st;
-    if (bytes > kScratchBytes) return GABOR_ERR_UNSUPPORTED;
+    if (L.bytes > kScratchBytes) return GABOR_ERR_UNSUPPORTED;
     void* ws = nullptr;
     if (scratch_address(&ws) != hipSuccess) return GABOR_ERR_DEVICE;
-    return gabor::adjoint_run(p, mfma, ws, d_grad_out, d_grad_image, grad_row_stride_elems,
+    return gabor::adjoint_run(p, L, ws, d_grad_out, 1, 0, d_grad_image, 0, grad_row_stride_elems,
                               (hipStream_t)hip_stream, false);
 }

@@ -65,11 +65,10 @@ void release(gabor_plan p)
     if (p->d_fjobs) (void)hipFree(p->d_fjobs);
     if (p->d_J) (void)hipFree(p->d_J);
     if (p->d_ajobs) (void)hipFree(p->d_ajobs);
-    if (p->d_adjP) (void)hipFree(p->d_adjP);
+    if (p->d_adjW) (void)hipFree(p->d_adjW);
     for (void* q : {(void*)p->d_ihj, (void*)p->d_ivj, (void*)p->d_itw, (void*)p->d_ifT, (void*)p->d_iJT,
                     (void*)p->d_iJ, (void*)p->d_iscr})
         if (q) (void)hipFree(q);
-    if (p->d_adjJ) (void)hipFree(p->d_adjJ);
     for (hipStream_t st : p->aux) (void)hipStreamDestroy(st);
     for (hipEvent_t e : p->fork_ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : p->join_ev) (void)hipEventDestroy(e);
@@ -138,7 +137,8 @@ struct RowPass {
 // One fused-kernel launch: all jobs of frequency i over the whole image,
 // strip segments of seg_rows rows.
 hipError_t launch_fused_freq(gabor_plan p, int i, const float* d_image, int64_t stride, void* d_out,
-                             int seg_rows, hipStream_t s)
+                             int seg_rows, hipStream_t s, int n_images = 1, int64_t img_bstride = 0,
+                             int64_t out_bstride = 0)
 {
     const FreqLaunch& fl = p->launches[i];
     StreamArgs sa{};
@@ -160,7 +160,11 @@ hipError_t launch_fused_freq(gabor_plan p, int i, const float* d_image, int64_t 
     sa.out_scale = fl.out_scale;
     sa.tap_scale[0] = fl.tap_scale[0];
     sa.tap_scale[1] = fl.tap_scale[1];
+    sa.n_images = n_images;
+    sa.img_bstride = img_bstride;
+    sa.out_bstride = out_bstride;
     if (fused_on_ws(p, i)) return launch_ws(p->fused_op, sa, fl.q, s);
+    if (n_images != 1) return hipErrorInvalidValue;
     return launch_stream(p->fused_op, sa, fl.q, s);
 }
 
@@ -312,6 +316,7 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
         }
 
         // Adjoint jobs: reversed taps k(R - T) of both passes, zero-padded to Kp.
+        p->adj_first.push_back((int)p->ajobs.size());
         for (size_t j = 0; j < fjobs.size(); ++j) {
             AdjJob aj{};
             aj.R = fd.R;
@@ -457,6 +462,7 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
         }
     }
 
+    p->adj_first.push_back((int)p->ajobs.size());
     for (int i = 0; i < n_freq; ++i) p->order.push_back(i);
     std::stable_sort(p->order.begin(), p->order.end(),
                      [&](int a, int b) { return p->freqs[a].R > p->freqs[b].R; });
@@ -778,78 +784,141 @@ extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int
     return GABOR_OK;
 }
 
-namespace gabor {
-
-// Which adjoint a plan takes and how much workspace it needs.  On the
-// matrix cores when every frequency runs in the fused kernel with a quarter
-// of at most 32: one partial plane per job (of the extended (H + 2R) x
-// (W + 2R) grid under the mirror rule, whose sum folds it back); otherwise
-// (zero boundary only) the vector-ALU kernels with one complex plane per
-// horizontal pass.
-gabor_status adjoint_workspace(gabor_plan p, bool* mfma_out, int64_t* bytes)
+extern "C" gabor_status gabor_bank_apply_batched(gabor_plan p, const float* d_images, int32_t n_images,
+                                                 int64_t image_stride_elems, int64_t row_stride_elems, void* d_out,
+                                                 void* hip_stream)
 {
-    if (p->iir) return GABOR_ERR_UNSUPPORTED;
-    const bool mirror = p->boundary == GABOR_BOUNDARY_MIRROR;
-    bool mfma = !p->launches.empty() && (!mirror || p->O <= kAdjFoldMaxFreq);
-    for (const FreqLaunch& fl : p->launches)
-        if (!fl.fused || fl.q > kAdjStreamMaxQuarter) mfma = false;
-    if (mirror && !mfma) return GABOR_ERR_UNSUPPORTED;
-    if (mfma) {
-        int64_t total = 0;
-        for (int i = 0; i < p->O; ++i) {
-            const int R = mirror ? p->freqs[i].R : 0;
-            total += (int64_t)p->launches[i].count * (p->H + 2 * R) * (p->W + 2 * R);
+    if (!p || n_images < 0) return GABOR_ERR_INVALID_ARG;
+    if (n_images == 0) return GABOR_OK;
+    if (!d_images || !d_out || row_stride_elems < p->W) return GABOR_ERR_INVALID_ARG;
+    const int64_t span = (int64_t)(p->H - 1) * row_stride_elems + p->W;
+    if (n_images > 1 && image_stride_elems < span) return GABOR_ERR_INVALID_ARG;
+    const int64_t out_bstride = (int64_t)p->O * p->N * p->H * p->W;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    bool one_launch = !p->iir && p->row_groups.empty();
+    for (int i = 0; i < p->O; ++i) one_launch = one_launch && fused_on_ws(p, i);
+    if (!one_launch) {
+        // plans with two-pass or four-wave frequencies: one apply per image
+        for (int b = 0; b < n_images; ++b) {
+            const gabor_status st = gabor_bank_apply(p, d_images + b * image_stride_elems, row_stride_elems,
+                                                     static_cast<float2*>(d_out) + b * out_bstride, hip_stream);
+            if (st != GABOR_OK) return st;
         }
-        *bytes = total * (int64_t)sizeof(float);
-    } else {
-        if (adj_row_lds_bytes(p->adj_max_kp) > 160 * 1024 || adj_col_lds_bytes(p->adj_max_kp) > 160 * 1024)
-            return GABOR_ERR_UNSUPPORTED;
-        *bytes = (int64_t)p->ajobs.size() * p->H * p->W * (int64_t)sizeof(float2);
+        return GABOR_OK;
     }
-    *mfma_out = mfma;
+    if (span >= (int64_t(1) << 30)) return GABOR_ERR_UNSUPPORTED;   // 32-bit buffer offsets per image
+    // every image in each frequency's launch; the launches fork and join as in gabor_bank_apply
+    const int n_aux = (int)p->aux.size();
+    if (n_aux > 0 && hipEventRecord(p->fork_ev[0], stream) != hipSuccess) return GABOR_ERR_DEVICE;
+    for (int k = 0; k < n_aux; ++k)
+        if (hipStreamWaitEvent(p->aux[k], p->fork_ev[0], 0) != hipSuccess) return GABOR_ERR_DEVICE;
+    for (size_t j = 0; j < p->order.size(); ++j) {
+        const int i = p->order[j];
+        const FreqLaunch& fl = p->launches[i];
+        hipStream_t ls = (j == 0 || n_aux == 0) ? stream : p->aux[(j - 1) % n_aux];
+        // profile name per batch size (the stat holds one launch's work)
+        LaunchTimer tm(p, ls,
+                       std::string(kWsNames[p->fused_op]) + "_r" + std::to_string(p->freqs[i].R) +
+                           (n_images > 1 ? "_x" + std::to_string(n_images) : std::string()),
+                       fl.macs * n_images, fl.bytes * n_images);
+        if (launch_fused_freq(p, i, d_images, row_stride_elems, d_out, fl.seg_rows, ls, n_images, image_stride_elems,
+                              out_bstride) != hipSuccess)
+            return GABOR_ERR_DEVICE;
+    }
+    for (int k = 0; k < n_aux; ++k)
+        if (hipEventRecord(p->join_ev[k], p->aux[k]) != hipSuccess ||
+            hipStreamWaitEvent(stream, p->join_ev[k], 0) != hipSuccess)
+            return GABOR_ERR_DEVICE;
     return GABOR_OK;
 }
 
-// The adjoint's launches, with the workspace the caller found (at least the
-// bytes adjoint_workspace reported; every byte of it that is read is first
-// written by the same call, so it needs no clearing).  `timed` brackets the
-// launches with profiling events when the plan's profiling is on.
-gabor_status adjoint_run(gabor_plan p, bool mfma, void* ws, const void* d_grad_out, float* d_grad_image,
-                         int64_t grad_row_stride_elems, hipStream_t stream, bool timed)
+namespace gabor {
+
+gabor_status adjoint_layout(const gabor_plan_s* p, AdjLayout* L)
 {
+    if (p->iir) return GABOR_ERR_UNSUPPORTED;
+    const bool mirror = p->boundary == GABOR_BOUNDARY_MIRROR;
+    if (mirror && p->O > kAdjFoldMaxFreq) return GABOR_ERR_UNSUPPORTED;
+    *L = AdjLayout{};
+    bool any_mfma = false;
+    for (int i = 0; i < p->O; ++i) {
+        const FreqLaunch& fl = p->launches[i];
+        const bool m = fl.fused && fl.q <= kAdjStreamMaxQuarter;
+        L->mfma.push_back(m ? 1 : 0);
+        any_mfma = any_mfma || m;
+        const int kp = p->freqs[i].Kp;
+        if (!m && (adj_row_lds_bytes(kp) > 160 * 1024 || adj_col_lds_bytes(kp) > 160 * 1024))
+            return GABOR_ERR_UNSUPPORTED;
+    }
+    auto align = [](int64_t b) { return (b + 255) / 256 * 256; };
+    L->direct = !mirror && !any_mfma;
+    if (L->direct) {
+        L->bytes = align((int64_t)p->ajobs.size() * p->H * p->W * (int64_t)sizeof(float2));
+        return GABOR_OK;
+    }
+    int64_t jc = 0;
+    for (int i = 0; i < p->O; ++i) {
+        const int off = mirror ? p->freqs[i].R : 0;
+        const int64_t Ho = p->H + 2 * off, Wo = p->W + 2 * off;
+        const int n_jobs = p->adj_first[i + 1] - p->adj_first[i];
+        const int planes = L->mfma[i] ? n_jobs : 1;
+        L->base.push_back(L->part_floats);
+        L->planes.push_back(planes);
+        L->part_floats += (int64_t)planes * Ho * Wo;
+        L->jbase.push_back(L->mfma[i] ? -1 : jc);
+        if (!L->mfma[i]) jc += (int64_t)n_jobs * p->H * Wo;
+    }
+    L->j_offset = align(L->part_floats * (int64_t)sizeof(float));
+    L->bytes = align(L->j_offset + jc * (int64_t)sizeof(float2));
+    return GABOR_OK;
+}
+
+gabor_status adjoint_run(gabor_plan p, const AdjLayout& L, void* ws, const void* d_grad_out, int n_images,
+                         int64_t g_bstride, float* d_grad, int64_t grad_bstride, int64_t grad_row_stride_elems,
+                         hipStream_t stream, bool timed)
+{
+    if (n_images <= 0) return GABOR_OK;
     const bool mirror = p->boundary == GABOR_BOUNDARY_MIRROR;
     const int64_t npix = (int64_t)p->H * p->W;
-    if (mfma) {
-        float* part = static_cast<float*>(ws);
-        const int n_planes = (int)p->fjobs.size();
-        // partial planes: [job][H][W], or [job][H + 2R][W + 2R] for the mirror rule
-        std::vector<int64_t> base(p->O);
-        int64_t total = 0;
-        for (int i = 0; i < p->O; ++i) {
-            const int R = mirror ? p->freqs[i].R : 0;
-            base[i] = total;
-            total += (int64_t)p->launches[i].count * (p->H + 2 * R) * (p->W + 2 * R);
-        }
-        LaunchTimer tm(p, stream, "adjoint_mfma_fp32", p->adj_row_macs + p->adj_col_macs,
-                       8 * (int64_t)p->O * p->N * npix + 4 * npix, timed);
-        // the frequencies run concurrently as in the forward apply
-        const int n_aux = (int)p->aux.size();
-        if (n_aux > 0 && hipEventRecord(p->fork_ev[0], stream) != hipSuccess) return GABOR_ERR_DEVICE;
-        for (int k = 0; k < n_aux; ++k)
-            if (hipStreamWaitEvent(p->aux[k], p->fork_ev[0], 0) != hipSuccess) return GABOR_ERR_DEVICE;
-        for (size_t j = 0; j < p->order.size(); ++j) {
-            const int i = p->order[j];
-            const FreqLaunch& fl = p->launches[i];
-            hipStream_t ls = (j == 0 || n_aux == 0) ? stream : p->aux[(j - 1) % n_aux];
+    const float2* G = static_cast<const float2*>(d_grad_out);
+    char* wsb = static_cast<char*>(ws);
+    bool all_mfma = !L.direct;
+    for (char m : L.mfma) all_mfma = all_mfma && m;
+    LaunchTimer tm(p, stream,
+                   std::string(L.direct ? "adjoint_fp32" : all_mfma ? "adjoint_mfma_fp32" : "adjoint_mixed_fp32") +
+                       (n_images > 1 ? "_x" + std::to_string(n_images) : std::string()),
+                   (p->adj_row_macs + p->adj_col_macs) * n_images,
+                   (8 * (int64_t)p->O * p->N * npix + 4 * npix) * n_images, timed);
+    if (L.direct) {
+        for (int b = 0; b < n_images; ++b)
+            if (launch_adjoint(G + b * g_bstride, p->H, p->W, 0, p->d_ajobs, (int)p->ajobs.size(), p->adj_max_kp,
+                               p->d_taps, reinterpret_cast<float2*>(wsb + b * L.bytes), d_grad + b * grad_bstride,
+                               grad_row_stride_elems, stream) != hipSuccess)
+                return GABOR_ERR_DEVICE;
+        return GABOR_OK;
+    }
+    const int64_t part_bstride = L.bytes / (int64_t)sizeof(float);
+    // the frequencies run concurrently as in the forward apply
+    const int n_aux = (int)p->aux.size();
+    if (n_aux > 0 && hipEventRecord(p->fork_ev[0], stream) != hipSuccess) return GABOR_ERR_DEVICE;
+    for (int k = 0; k < n_aux; ++k)
+        if (hipStreamWaitEvent(p->aux[k], p->fork_ev[0], 0) != hipSuccess) return GABOR_ERR_DEVICE;
+    for (size_t j = 0; j < p->order.size(); ++j) {
+        const int i = p->order[j];
+        const FreqLaunch& fl = p->launches[i];
+        hipStream_t ls = (j == 0 || n_aux == 0) ? stream : p->aux[(j - 1) % n_aux];
+        const int off = mirror ? p->freqs[i].R : 0;
+        const int Ho = p->H + 2 * off, Wo = p->W + 2 * off;
+        if (L.mfma[i]) {
             AdjStreamArgs a{};
-            a.G = (const float2*)d_grad_out;
-            a.part = part + base[i];
+            a.G = G;
+            a.part = reinterpret_cast<float*>(wsb) + L.base[i];
             a.H = p->H;
             a.W = p->W;
             a.R = p->freqs[i].R;
-            a.off = mirror ? a.R : 0;
-            a.Ho = p->H + 2 * a.off;
-            a.Wo = p->W + 2 * a.off;
+            a.off = off;
+            a.Ho = Ho;
+            a.Wo = Wo;
             // segments of a multiple of 32 rows unless one covers the grid
             int seg = fl.seg_rows;
             if (seg % 32 != 0 && seg < a.Ho) seg = (seg + 31) / 32 * 32;
@@ -859,60 +928,122 @@ gabor_status adjoint_run(gabor_plan p, bool mfma, void* ws, const void* d_grad_o
             a.n_jobs = fl.count;
             a.jobs = p->d_fjobs + fl.first;
             a.taps = p->d_taps;
+            a.n_images = n_images;
+            a.g_bstride = g_bstride;
+            a.part_bstride = part_bstride;
             if (launch_adjoint_stream(a, fl.q, ls) != hipSuccess) return GABOR_ERR_DEVICE;
+        } else {
+            const int first = p->adj_first[i], n_jobs = p->adj_first[i + 1] - first;
+            for (int b = 0; b < n_images; ++b) {
+                char* w = wsb + b * L.bytes;
+                if (launch_adjoint(G + b * g_bstride, p->H, p->W, off, p->d_ajobs + first, n_jobs,
+                                   p->freqs[i].Kp, p->d_taps, reinterpret_cast<float2*>(w + L.j_offset) + L.jbase[i],
+                                   reinterpret_cast<float*>(w) + L.base[i], Wo, ls) != hipSuccess)
+                    return GABOR_ERR_DEVICE;
+            }
         }
-        for (int k = 0; k < n_aux; ++k)
-            if (hipEventRecord(p->join_ev[k], p->aux[k]) != hipSuccess ||
-                hipStreamWaitEvent(stream, p->join_ev[k], 0) != hipSuccess)
-                return GABOR_ERR_DEVICE;
-        if (mirror) {
-            AdjFoldArgs fa{};
-            fa.part = part;
-            fa.grad = d_grad_image;
-            fa.grad_stride = grad_row_stride_elems;
-            fa.H = p->H;
-            fa.W = p->W;
-            fa.n_freq = p->O;
-            for (int i = 0; i < p->O; ++i) fa.f[i] = AdjFoldFreq{base[i], p->freqs[i].R, p->launches[i].count};
-            return launch_adjoint_fold_sum(fa, stream) == hipSuccess ? GABOR_OK : GABOR_ERR_DEVICE;
-        }
-        return launch_adjoint_sum(part, n_planes, p->H, p->W, d_grad_image, grad_row_stride_elems, stream) ==
-                       hipSuccess
-                   ? GABOR_OK
-                   : GABOR_ERR_DEVICE;
     }
-    LaunchTimer tm(p, stream, "adjoint_fp32", p->adj_row_macs + p->adj_col_macs,
-                   8 * (int64_t)p->O * p->N * npix + 4 * npix, timed);
-    return launch_adjoint((const float2*)d_grad_out, p->H, p->W, p->d_ajobs, (int)p->ajobs.size(), p->adj_max_kp,
-                          p->d_taps, static_cast<float2*>(ws), d_grad_image, grad_row_stride_elems, stream) ==
-                   hipSuccess
+    for (int k = 0; k < n_aux; ++k)
+        if (hipEventRecord(p->join_ev[k], p->aux[k]) != hipSuccess ||
+            hipStreamWaitEvent(stream, p->join_ev[k], 0) != hipSuccess)
+            return GABOR_ERR_DEVICE;
+    if (mirror) {
+        AdjFoldArgs fa{};
+        fa.part = reinterpret_cast<const float*>(wsb);
+        fa.grad = d_grad;
+        fa.grad_stride = grad_row_stride_elems;
+        fa.H = p->H;
+        fa.W = p->W;
+        fa.n_freq = p->O;
+        fa.n_images = n_images;
+        fa.part_bstride = part_bstride;
+        fa.grad_bstride = grad_bstride;
+        for (int i = 0; i < p->O; ++i) fa.f[i] = AdjFoldFreq{L.base[i], p->freqs[i].R, L.planes[i]};
+        return launch_adjoint_fold_sum(fa, stream) == hipSuccess ? GABOR_OK : GABOR_ERR_DEVICE;
+    }
+    int total = 0;
+    for (int n : L.planes) total += n;
+    return launch_adjoint_sum(reinterpret_cast<const float*>(wsb), total, p->H, p->W, d_grad, grad_row_stride_elems,
+                              n_images, part_bstride, grad_bstride, stream) == hipSuccess
                ? GABOR_OK
                : GABOR_ERR_DEVICE;
 }
 
 }  // namespace gabor
 
+namespace {
+
+// The plan's adjoint workspace, grown to at least `bytes` (after the work
+// already queued on `stream`, which every adjoint call joins back to, has
+// finished with the old one).
+gabor_status adjoint_reserve(gabor_plan p, int64_t bytes, hipStream_t stream)
+{
+    if (p->d_adjW && p->adj_cap >= bytes) return GABOR_OK;
+    if (env_flag("LIBGABOR_FAIL_ALLOC")) return GABOR_ERR_OUT_OF_MEMORY;
+    if (p->d_adjW) {
+        if (hipStreamSynchronize(stream) != hipSuccess) return GABOR_ERR_DEVICE;
+        (void)hipFree(p->d_adjW);
+        p->d_adjW = nullptr;
+        p->workspace_bytes -= p->adj_cap;
+        p->adj_cap = 0;
+    }
+    void* d = nullptr;
+    const hipError_t e = hipMalloc(&d, (size_t)bytes);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? GABOR_ERR_OUT_OF_MEMORY : GABOR_ERR_DEVICE;
+    p->d_adjW = d;
+    p->adj_cap = bytes;
+    p->workspace_bytes += bytes;
+    return GABOR_OK;
+}
+
+// Workspace bound of one batched adjoint launch group: images beyond it run
+// in further groups.
+constexpr int64_t kAdjBatchBytes = int64_t(1) << 30;
+
+}  // namespace
+
 extern "C" gabor_status gabor_bank_apply_adjoint(gabor_plan p, const void* d_grad_out, float* d_grad_image,
                                                  int64_t grad_row_stride_elems, void* hip_stream)
 {
     if (!p || !d_grad_out || !d_grad_image) return GABOR_ERR_INVALID_ARG;
     if (grad_row_stride_elems < p->W) return GABOR_ERR_INVALID_ARG;
-    bool mfma = false;
-    int64_t bytes = 0;
-    const gabor_status st = adjoint_workspace(p, &mfma, &bytes);
+    AdjLayout L;
+    gabor_status st = adjoint_layout(p, &L);
     if (st != GABOR_OK) return st;
+    hipStream_t stream = (hipStream_t)hip_stream;
     // the plan keeps its adjoint workspace from the first call on
-    if (mfma ? !p->d_adjP : !p->d_adjJ) {
-        if (env_flag("LIBGABOR_FAIL_ALLOC")) return GABOR_ERR_OUT_OF_MEMORY;
-        void* d = nullptr;
-        const hipError_t e = hipMalloc(&d, (size_t)bytes);
-        if (e != hipSuccess) return e == hipErrorOutOfMemory ? GABOR_ERR_OUT_OF_MEMORY : GABOR_ERR_DEVICE;
-        if (mfma) p->d_adjP = static_cast<float*>(d);
-        else p->d_adjJ = static_cast<float2*>(d);
-        p->workspace_bytes += bytes;
+    if ((st = adjoint_reserve(p, L.bytes, stream)) != GABOR_OK) return st;
+    return adjoint_run(p, L, p->d_adjW, d_grad_out, 1, 0, d_grad_image, 0, grad_row_stride_elems, stream, true);
+}
+
+extern "C" gabor_status gabor_bank_apply_adjoint_batched(gabor_plan p, const void* d_grad_out, int32_t n_images,
+                                                         float* d_grad_images, int64_t grad_image_stride_elems,
+                                                         int64_t grad_row_stride_elems, void* hip_stream)
+{
+    if (!p || n_images < 0) return GABOR_ERR_INVALID_ARG;
+    if (n_images == 0) return GABOR_OK;
+    if (!d_grad_out || !d_grad_images) return GABOR_ERR_INVALID_ARG;
+    if (grad_row_stride_elems < p->W ||
+        (n_images > 1 && grad_image_stride_elems < (int64_t)(p->H - 1) * grad_row_stride_elems + p->W))
+        return GABOR_ERR_INVALID_ARG;
+    AdjLayout L;
+    gabor_status st = adjoint_layout(p, &L);
+    if (st != GABOR_OK) return st;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    // LIBGABOR_ADJ_BATCH_BYTES lowers the group bound (tests of the grouping)
+    int64_t cap = kAdjBatchBytes;
+    if (const char* v = std::getenv("LIBGABOR_ADJ_BATCH_BYTES")) cap = std::max<int64_t>(1, std::atoll(v));
+    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(n_images, cap / L.bytes));
+    if ((st = adjoint_reserve(p, (int64_t)chunk * L.bytes, stream)) != GABOR_OK) return st;
+    const int64_t g_bstride = (int64_t)p->O * p->N * p->H * p->W;
+    const float2* G = static_cast<const float2*>(d_grad_out);
+    for (int b0 = 0; b0 < n_images; b0 += chunk) {
+        const int n = std::min(chunk, n_images - b0);
+        st = adjoint_run(p, L, p->d_adjW, G + b0 * g_bstride, n, g_bstride, d_grad_images + b0 * grad_image_stride_elems,
+                         grad_image_stride_elems, grad_row_stride_elems, stream, true);
+        if (st != GABOR_OK) return st;
     }
-    void* ws = mfma ? static_cast<void*>(p->d_adjP) : static_cast<void*>(p->d_adjJ);
-    return adjoint_run(p, mfma, ws, d_grad_out, d_grad_image, grad_row_stride_elems, (hipStream_t)hip_stream, true);
+    return GABOR_OK;
 }
 
 // Segment heights the tuner tries for one fused launch, up to the image

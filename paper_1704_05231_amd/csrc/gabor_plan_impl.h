@@ -40,11 +40,12 @@ struct gabor_plan_s {
     std::vector<FreqLaunch> launches;      // per frequency
     std::vector<int> order;                // launch order of the frequencies
     std::vector<AdjJob> ajobs;             // adjoint jobs (every horizontal result)
+    std::vector<int> adj_first;            // per frequency: its first adjoint job (O + 1 entries)
     int adj_max_kp = 0;
     int64_t adj_row_macs = 0, adj_col_macs = 0;
     AdjJob* d_ajobs = nullptr;
-    float2* d_adjJ = nullptr;              // adjoint workspace, allocated by the first adjoint call
-    float* d_adjP = nullptr;   // matrix-core adjoint: one partial plane per job (at first use)
+    void* d_adjW = nullptr;                // adjoint workspace (allocated, and grown, by adjoint calls)
+    int64_t adj_cap = 0;                   // its bytes
     // recursive-smoother variant (gabor_bank_plan_iir)
     bool iir = false;
     int32_t n_ihj = 0, n_ivj = 0;
@@ -87,11 +88,31 @@ inline bool fused_on_ws(const gabor_plan_s* p, int i)
 // The plan's frequency table as the batch kernels read it (R, segment rows,
 // scales, quarter per frequency).
 std::vector<BatchFreq> batch_freq_table(const gabor_plan_s* p);
-// Adjoint of the bank (gabor_plan.cpp): which kernels a plan's adjoint runs
-// (mfma: the matrix-core kernels) and the workspace bytes they need; then
-// the launches with a caller-provided workspace of at least that size.
-gabor_status adjoint_workspace(gabor_plan p, bool* mfma, int64_t* bytes);
-gabor_status adjoint_run(gabor_plan p, bool mfma, void* ws, const void* d_grad_out, float* d_grad_image,
-                         int64_t grad_row_stride_elems, hipStream_t stream, bool timed);
+// Adjoint of the bank (gabor_plan.cpp).  Per frequency, the matrix-core
+// kernel (fused frequencies of quarter <= 32: one partial plane per job) or
+// the vector-ALU kernels (one partial plane); the planes lie on the image
+// grid (zero boundary) or on the image extended by the frequency's R (mirror
+// rule), and a last launch sums (or folds and sums) them into dL/df.  A
+// zero-boundary plan with no matrix-core frequency runs the vector kernels
+// once over every job, straight into dL/df.
+struct AdjLayout {
+    bool direct = false;
+    std::vector<char> mfma;        // per frequency
+    std::vector<int64_t> base;     // first float of its partial planes
+    std::vector<int> planes;       // its partial planes
+    std::vector<int64_t> jbase;    // first complex of its J planes (vector ALU)
+    int64_t part_floats = 0;       // all partial planes
+    int64_t j_offset = 0;          // bytes from an image's workspace to its J planes
+    int64_t bytes = 0;             // workspace per image (a multiple of 256)
+};
+gabor_status adjoint_layout(const gabor_plan_s* p, AdjLayout* L);
+// The launches for n_images images (G of image b at d_grad_out + b *
+// g_bstride complex elements, its gradient at d_grad + b * grad_bstride) with
+// a caller-provided workspace of at least n_images * L.bytes bytes; every
+// byte of it that is read is first written by the same call.  `timed`
+// brackets the launches with profiling events when profiling is on.
+gabor_status adjoint_run(gabor_plan p, const AdjLayout& L, void* ws, const void* d_grad_out, int n_images,
+                         int64_t g_bstride, float* d_grad, int64_t grad_bstride, int64_t grad_row_stride_elems,
+                         hipStream_t stream, bool timed);
 }  // namespace gabor
 

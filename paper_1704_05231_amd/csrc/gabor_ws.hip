@@ -410,7 +410,15 @@ __device__ __forceinline__ void ws_body(const StreamArgs& a, const FusedJob& jb,
 template <int OP, int Q>
 __global__ __launch_bounds__(kWThreads) void k_ws(StreamArgs a)
 {
-    const int lid = xcd_local_id(blockIdx.x, gridDim.x);
+    int lid = xcd_local_id(blockIdx.x, gridDim.x);
+    if (a.n_images > 1) {
+        // strided batch: image-major workgroup ids, each image's own grid after
+        const int per = a.n_xs * a.n_ys * a.n_jobs;
+        const int b = lid / per;
+        lid -= b * per;
+        a.img += b * a.img_bstride;
+        a.out += b * a.out_bstride;
+    }
     const FusedJob jb = a.jobs[lid % a.n_jobs];
     const int rest = lid / a.n_jobs;
     if (jb.j_real) ws_body<OP, Q, true, false>(a, jb, rest);
@@ -558,7 +566,8 @@ hipError_t launch_ws(int op, const StreamArgs& a, int Q, hipStream_t stream)
     if (!ws_supported(op, Q) || a.seg_rows <= 0 || a.seg_rows % 16 != 0 || 16 + 2 * a.R > 4 * Q)
         return hipErrorInvalidValue;
     if ((int64_t)a.H * a.W * 8 > (int64_t(1) << 30)) return hipErrorInvalidValue;
-    const long long nb = (long long)a.n_xs * a.n_ys * a.n_jobs;
+    if (a.n_images > 1 && (a.img_bstride < 0 || a.out_bstride < 0)) return hipErrorInvalidValue;
+    const long long nb = (long long)a.n_xs * a.n_ys * a.n_jobs * (a.n_images > 1 ? a.n_images : 1);
     if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidValue;
     switch (op) {
         case FUSED_F32: return ws_form<FUSED_F32>(a, Q, (int)nb, stream);

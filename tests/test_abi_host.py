@@ -133,6 +133,14 @@ def test_adjoint_rejects_null_arguments():
     lib = binding.load()
     assert lib.gabor_bank_apply_adjoint(None, ctypes.c_void_p(16), ctypes.c_void_p(16), 8, None) == 1
     assert lib.gabor_bank_apply_adjoint_noalloc(None, ctypes.c_void_p(16), ctypes.c_void_p(16), 8, None) == 1
+    assert lib.gabor_bank_apply_adjoint_batched(None, ctypes.c_void_p(16), 2, ctypes.c_void_p(16), 64, 8,
+                                                None) == 1
+
+
+def test_batched_apply_rejects_null_arguments():
+    lib = binding.load()
+    assert lib.gabor_bank_apply_batched(None, ctypes.c_void_p(16), 2, 64, 8, ctypes.c_void_p(16), None) == 1
+    assert lib.gabor_bank_apply_batched(None, ctypes.c_void_p(16), -1, 64, 8, ctypes.c_void_p(16), None) == 1
 
 
 def test_batch_rejects_null_arguments():

@@ -2,9 +2,9 @@
 autograd layer built on it (FP32).
 
 1. Dot-product identity: <bank(f), G> = <f, adjoint(G)> for random f and G,
-   with <F, G> = sum Re(conj(G) F), both sides summed in FP64; zero boundary
-   on both adjoint paths, and the mirror rule (the transpose of the fold) on
-   the matrix-core one, including images smaller than the band.
+   with <F, G> = sum Re(conj(G) F), both sides summed in FP64; both boundary
+   rules (the mirror rule's adjoint is the transpose of the fold) on both
+   adjoint paths, including images smaller than the band.
 2. The oracle's FP64 gradient of L = mean |F|^2 at sampled pixels.
 3. Central finite differences of the same loss (h = 1e-3) at sampled pixels,
    each difference formed as an FP64 sum over the outputs within R of the
@@ -38,10 +38,12 @@ def make_bank(gpu_lib, H, W, om, sg, N, th, boundary="zero"):
     return gpu_lib.GaborBank(H, W, om, sg, N, th, 3.0, boundary, "fp32")
 
 
-# "fused": the matrix-core adjoint of fused plans (both boundary rules; for
-# the mirror rule the transpose of the fold); "twopass": plans on the
-# two-pass kernels take the vector-ALU adjoint (zero boundary)
-@pytest.mark.parametrize("path,boundary", [("fused", "zero"), ("fused", "mirror"), ("twopass", "zero")])
+# "fused": the matrix-core adjoint of fused plans; "twopass": plans on the
+# two-pass kernels take the vector-ALU adjoint (straight into dL/df under the
+# zero boundary, one extended partial plane per frequency, folded, under the
+# mirror rule)
+@pytest.mark.parametrize("path,boundary", [("fused", "zero"), ("fused", "mirror"), ("twopass", "zero"),
+                                           ("twopass", "mirror")])
 @pytest.mark.parametrize("case", range(len(BANKS)))
 def test_adjoint_dot_product_identity(gpu_lib, case, path, boundary, monkeypatch):
     import torch
@@ -76,18 +78,6 @@ def test_adjoint_row_stride_and_overwrite(gpu_lib):
     torch.cuda.synchronize()
     assert torch.equal(a, b)
     assert torch.isnan(buf[:, W:]).all()          # padding columns untouched
-    bank.close()
-
-
-def test_adjoint_mirror_two_pass_plan_is_unsupported(gpu_lib, monkeypatch):
-    # the transpose of the fold exists only in the matrix-core adjoint
-    import torch
-    monkeypatch.setenv("LIBGABOR_ALGO", "twopass")
-    bank = gpu_lib.GaborBank(16, 16, [1.0], [2.0], 4, None, 3.0, "mirror", "fp32")
-    G = torch.zeros((1, 4, 16, 16), dtype=torch.complex64, device="cuda")
-    with pytest.raises(gpu_lib.GaborError) as ei:
-        bank.adjoint(G)
-    assert ei.value.status == 4
     bank.close()
 
 
@@ -239,13 +229,13 @@ def test_feature_layer_finite_differences_64_pixels(gpu_lib):
 
 
 def draw(seed):
-    """Shape, frequencies, radii, orientations and rule; the mirror rule's
-    adjoint (transpose of the fold) is on the matrix cores, which take radii
-    up to 56, the zero rule's any radius (beyond that the vector-ALU adjoint)."""
+    """Shape, frequencies, radii, orientations and rule; radii up to 56 take
+    the matrix-core adjoint, larger ones the vector-ALU one (mixed plans take
+    both, one per frequency)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     H, W = int(rng.integers(1, 80)), int(rng.integers(1, 90))
     boundary = "mirror" if rng.integers(0, 2) else "zero"
-    choices = [0, 1, 3, 6, 10, 20, 27, 30, 40, 45, 56] + ([] if boundary == "mirror" else [70, 88, 104, 110])
+    choices = [0, 1, 3, 6, 10, 20, 27, 30, 40, 45, 56, 70, 88, 104, 110]
     n_freq = int(rng.integers(1, 3))
     radii = [int(rng.choice(choices)) for _ in range(n_freq)]
     sigmas = [r / 3.0 if r > 0 else 0.1 for r in radii]
@@ -271,3 +261,65 @@ def test_adjoint_random_dot_product_identity(gpu_lib, seed):
     radii = [int(math.floor(3 * s + 0.5)) for s in sg]
     print(f"adjoint seed {seed}: {H}x{W} N={N} R={radii} {bnd}: rel {abs(lhs - rhs) / scale:.2e}")
     assert abs(lhs - rhs) <= 1e-6 * scale
+
+
+def mirror_fd(gpu_lib, img, om, sg, N, n_px, seed, h):
+    """Central differences (step h, the FP32 image's actual steps) of
+    L = mean |F|^2 under the mirror rule, summing |F|^2 over every output
+    in FP64 (the outputs the pixel does not reach are bitwise equal in the
+    two forwards and cancel)."""
+    import torch
+    H, W = img.shape
+    bank = gpu_lib.GaborBank(H, W, om, sg, N, None, 3.0, "mirror", "fp32")
+    n = len(om) * N * H * W
+    xs, ys = workloads.sample_pixels(H, W, n_px, seed)
+    base = torch.from_numpy(img).cuda()
+    fd = np.empty(len(xs))
+    for i, (x, y) in enumerate(zip(xs, ys)):
+        vals, steps = [], []
+        for sgn in (+1, -1):
+            v = np.float32(img[y, x] + np.float32(sgn * h))
+            steps.append(abs(float(v) - float(img[y, x])))
+            pert = base.clone()
+            pert[y, x] = float(v)
+            F = bank(pert)
+            vals.append(float(torch.sum(torch.abs(F.to(torch.complex128)) ** 2)) / n)
+        fd[i] = (vals[0] - vals[1]) / (steps[0] + steps[1])
+    bank.close()
+    return fd, xs, ys
+
+
+@pytest.mark.parametrize("R", [75, 96])
+def test_adjoint_mirror_large_radius(gpu_lib, R):
+    """Mirror rule beyond the matrix-core adjoint's reach (R = 75, 96: the
+    vector-ALU adjoint on the image extended by R, folded back; R = 96 is
+    larger than the image's half-width, so positions fold more than once),
+    beside a matrix-core frequency: dot-product identity, then the layer's
+    gradient against central finite differences at 16 pixels.  L is
+    quadratic in f, so a central difference has no truncation error at any
+    step: h = 0.25 keeps the FP32 rounding of the roughly 2 x 10^5 outputs a
+    pixel reaches at R = 96 (their |F|^2 summed twice) well below the
+    difference itself, where h = 1e-3 leaves it near 1e-3 of the peak."""
+    import torch
+    H, W = 100, 120
+    sg = [R / 3.0, 2.0]
+    om = [math.pi / (2 * sg[0]), math.pi / 2]
+    N = 4
+    bank = make_bank(gpu_lib, H, W, om, sg, N, None, "mirror")
+    rng = np.random.Generator(np.random.PCG64(600 + R))
+    f = rng.uniform(-1, 1, (H, W)).astype(np.float32)
+    G = (rng.uniform(-1, 1, (2, N, H, W)) + 1j * rng.uniform(-1, 1, (2, N, H, W))).astype(np.complex64)
+    F = bank(torch.from_numpy(f).cuda()).cpu().numpy()
+    g = bank.adjoint(torch.from_numpy(G).cuda()).cpu().numpy()
+    bank.close()
+    lhs = np.sum((np.conj(G.astype(np.complex128)) * F.astype(np.complex128)).real)
+    rhs = np.sum(f.astype(np.float64) * g.astype(np.float64))
+    scale = np.sum(np.abs(G) * np.abs(F))
+    print(f"mirror R={R}: dot-product rel {abs(lhs - rhs) / scale:.2e}")
+    assert abs(lhs - rhs) <= 1e-6 * scale
+    img = workloads.uniform_image(H, W, 610 + R)
+    grad = loss_grad_gpu(gpu_lib, img, om, sg, N, None, "mirror")
+    fd, xs, ys = mirror_fd(gpu_lib, img, om, sg, N, 16, 620 + R, 0.25)
+    err = np.abs(fd - grad[ys, xs]).max() / np.abs(grad[ys, xs]).max()
+    print(f"mirror R={R} finite differences: max err / peak {err:.2e}")
+    assert err <= 1e-4
