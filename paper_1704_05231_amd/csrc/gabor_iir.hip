@@ -14,6 +14,8 @@
 // whole extended line are kept in a scratch plane for the backward pass.
 // Modulation and demodulation use FP32 twiddles of the unfolded coordinate,
 // computed in FP64 on the host.
+#include <type_traits>
+
 #include "gabor_internal.h"
 
 namespace gabor {
@@ -195,11 +197,215 @@ __global__ __launch_bounds__(64 * kIirChunks) void k_iir_block(const IirJob* __r
     }
 }
 
+// The same recursion with every chunk's samples held in registers (no
+// scratch plane): kIirRegChunks = 64 chunks per line, 512 / 64 = 8 columns
+// per workgroup, eight chunks per wave (lanes 8 c .. 8 c + 7 take chunk
+// 8 w + c); short chunks keep the registers low enough for two workgroups
+// per compute unit, so one's loads overlap the other's arithmetic.  Every chunk holds exactly LC samples (the job's lc): the
+// line is padded with zeros in front (a recursion from rest over zeros stays
+// at rest), so every loop is straight-line code.  The input is read once: after the
+// carry, the true forward result of a chunk is its zero-state result plus
+// the zero-input response of its entering state (the recursion is linear),
+// so nothing is rerun from the input; likewise backward.
+constexpr int kIirRegCols = 512 / kIirRegChunks;
+template <int LC>
+__global__ __launch_bounds__(512) void k_iir_reg(const IirJob* __restrict__ jobs, const float2* __restrict__ tw,
+                                                 int boundary, float2* __restrict__ out_base)
+{
+    constexpr int CH = kIirRegChunks, NC = kIirRegCols;
+    __shared__ double sc[CH][6][NC];                      // carry scan: 3 complex FP64 states per chunk
+    __shared__ float2 tws[CH * kIirRegMaxChunk];          // the job's twiddles, staged once
+    const IirJob jb = jobs[blockIdx.y];
+    const int lane = threadIdx.x & 63;
+    const int cl = lane % NC, chunk = (64 / NC) * (threadIdx.x >> 6) + lane / NC;
+    const int col = blockIdx.x * NC + cl;
+    const bool live = col < jb.cols;
+    const int n = jb.n, T = jb.T, ext = n + 2 * T;
+    constexpr int lc = LC;                                         // the host sets jb.lc = LC
+    const int m0 = ext - (CH - chunk) * lc;                        // first sample (< 0: padding)
+    const float a0 = jb.a[0], a1 = jb.a[1], a2 = jb.a[2], a3 = jb.a[3];
+    // (cos, sin)(w l), l = -T .. n + T - 1, into LDS (ext <= CH * kIirRegMaxChunk)
+    for (int i = threadIdx.x; i < ext; i += 512) tws[i] = tw[jb.tw_off + i];
+
+    auto rec = [&](float2 u, float2& s1, float2& s2, float2& s3) {
+        float2 w;
+        w.x = a0 * u.x - a1 * s1.x - a2 * s2.x - a3 * s3.x;
+        w.y = a0 * u.y - a1 * s1.y - a2 * s2.y - a3 * s3.y;
+        s3 = s2;
+        s2 = s1;
+        s1 = w;
+        return w;
+    };
+    auto hom = [&](float2& s1, float2& s2, float2& s3) {       // zero-input step
+        float2 w;
+        w.x = -a1 * s1.x - a2 * s2.x - a3 * s3.x;
+        w.y = -a1 * s1.y - a2 * s2.y - a3 * s3.y;
+        s3 = s2;
+        s2 = s1;
+        s1 = w;
+        return w;
+    };
+    // Entering states across the chunks (FP64, as in k_iir_block), as a
+    // parallel scan: chunk c maps its entering state s to z_c + P s (z_c its
+    // zero-state final state, P = A^lc), so the true final state is
+    // S_c = sum over j <= c of P^(c - j) z_j (forward; mirrored backward).
+    // Hillis-Steele over the 64 chunks in six steps, step k adding
+    // P^(2^k) times the value 2^k chunks back; then chunk c enters with
+    // S_(c - 1) (forward) or S_(c + 1) (backward), zero at the line's end.
+    auto carry = [&](bool forward, float2& e1, float2& e2, float2& e3) {
+        double z[6] = {e1.x, e1.y, e2.x, e2.y, e3.x, e3.y};
+        static_assert(CH == 64, "six scan steps");
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int d = 1 << k;
+            const double* P = k == 0 ? jb.apow : jb.apow2[k - 1];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) sc[chunk][i][cl] = z[i];
+            __syncthreads();
+            const int src = forward ? chunk - d : chunk + d;
+            if (src >= 0 && src < CH) {
+                double y[6];
+#pragma unroll
+                for (int i = 0; i < 6; ++i) y[i] = sc[src][i][cl];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    z[2 * r] += P[3 * r] * y[0] + P[3 * r + 1] * y[2] + P[3 * r + 2] * y[4];
+                    z[2 * r + 1] += P[3 * r] * y[1] + P[3 * r + 1] * y[3] + P[3 * r + 2] * y[5];
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) sc[chunk][i][cl] = z[i];
+        __syncthreads();
+        const int src = forward ? chunk - 1 : chunk + 1;
+        double y[6] = {0, 0, 0, 0, 0, 0};
+        if (src >= 0 && src < CH)
+#pragma unroll
+            for (int i = 0; i < 6; ++i) y[i] = sc[src][i][cl];
+        e1 = make_float2((float)y[0], (float)y[1]);
+        e2 = make_float2((float)y[2], (float)y[3]);
+        e3 = make_float2((float)y[4], (float)y[5]);
+        __syncthreads();                                  // sc is reused
+    };
+
+    float2 buf[LC];
+    const float2 zero = make_float2(0.f, 0.f);
+    // ---- the chunk's input samples.  Source rows follow the boundary rule
+    // incrementally: u = m - T walks the line; under the mirror rule its
+    // residue q modulo 2(n - 1) folds to q or 2(n - 1) - q.  Every load is
+    // issued unconditionally (row clamped, value selected), so they are all
+    // in flight together.
+    const int p = 2 * (n - 1);
+    int u = m0 - T;
+    int q = 0;
+    if (boundary != 0 && p > 0) {
+        q = u % p;
+        if (q < 0) q += p;
+    }
+    const int64_t ccol = live ? col : 0;
+    auto load_all = [&](auto complex_in, auto mirror) {
+#pragma unroll
+        for (int k = 0; k < LC; ++k) {
+            int r;
+            if constexpr (mirror) r = p > 0 ? (q < n ? q : p - q) : 0;
+            else r = (u >= 0 && u < n) ? u : -1;
+            const bool ok = live && r >= 0 && u + T >= 0;      // u + T < 0: front padding
+            const int64_t at = (int64_t)max(r, 0) * jb.in_stride + ccol;
+            if constexpr (complex_in) {
+                const float2 v = reinterpret_cast<const float2*>(jb.in)[at];
+                buf[k] = make_float2(ok ? v.x : 0.f, ok ? (jb.conj ? -v.y : v.y) : 0.f);
+            } else {
+                const float v = reinterpret_cast<const float*>(jb.in)[at];
+                buf[k] = make_float2(ok ? v : 0.f, 0.f);
+            }
+            ++u;
+            if constexpr (mirror) q = q + 1 == p ? 0 : q + 1;
+        }
+    };
+    using tt = std::true_type;
+    using ff = std::false_type;
+    if (jb.in_complex) {
+        if (boundary != 0) load_all(tt{}, tt{});
+        else load_all(tt{}, ff{});
+    } else {
+        if (boundary != 0) load_all(ff{}, tt{});
+        else load_all(ff{}, ff{});
+    }
+    __syncthreads();                                      // twiddles staged
+    // ---- forward (causal): zero-state pass over the modulated inputs
+    // u = v exp(-i w l)
+    float2 w1 = zero, w2 = zero, w3 = zero;
+#pragma unroll
+    for (int k = 0; k < LC; ++k) {
+            const float2 t = tws[max(m0 + k, 0)], v = buf[k];
+            buf[k] = rec(make_float2(v.x * t.x + v.y * t.y, v.y * t.x - v.x * t.y), w1, w2, w3);
+        }
+    carry(true, w1, w2, w3);
+#pragma unroll
+    for (int k = 0; k < LC; ++k) {
+            const float2 h = hom(w1, w2, w3);
+            buf[k].x += h.x;
+            buf[k].y += h.y;
+        }
+    // ---- backward (anti-causal): zero-state pass over the forward results
+    w1 = w2 = w3 = zero;
+#pragma unroll
+    for (int k = LC - 1; k >= 0; --k) buf[k] = rec(buf[k], w1, w2, w3);
+    carry(false, w1, w2, w3);
+    // entering-state response, then demodulate the image samples
+    float2* out = (jb.out ? jb.out : out_base + (int64_t)jb.out_plane * n * jb.cols) + col;
+#pragma unroll
+    for (int k = LC - 1; k >= 0; --k) {
+            const float2 h = hom(w1, w2, w3);
+            const float2 v = make_float2(buf[k].x + h.x, buf[k].y + h.y);
+            const int l = m0 + k - T;
+            if (live && l >= 0 && l < n) {
+                const float2 t = tws[m0 + k];
+                out[(int64_t)l * jb.out_stride] = make_float2(v.x * t.x - v.y * t.y, v.x * t.y + v.y * t.x);
+            }
+        }
+}
+
+template <int LC>
+hipError_t launch_iir_reg(const IirJob* d_jobs, int n_jobs, int cols, const float2* d_tw, int boundary,
+                          float2* d_out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_iir_reg<LC>, dim3((cols + kIirRegCols - 1) / kIirRegCols, n_jobs), dim3(512), 0, stream,
+                       d_jobs, d_tw, boundary, d_out);
+    return hipGetLastError();
+}
+
+// One pass: the register kernel when the jobs' chunks (of kIirRegChunks per
+// line) fit, else the scratch-plane one (kIirChunks per line).
+hipError_t launch_iir_pass(const IirJob* d_jobs, int n_jobs, int cols, int max_lc, bool reg, const float2* d_tw,
+                           int boundary, float2* d_out, hipStream_t stream)
+{
+    if (reg) {
+        // every job of the pass has lc = max_lc, a multiple of 8 from 8 to 64
+        switch (max_lc) {
+            case 8: return launch_iir_reg<8>(d_jobs, n_jobs, cols, d_tw, boundary, d_out, stream);
+            case 16: return launch_iir_reg<16>(d_jobs, n_jobs, cols, d_tw, boundary, d_out, stream);
+            case 24: return launch_iir_reg<24>(d_jobs, n_jobs, cols, d_tw, boundary, d_out, stream);
+            case 32: return launch_iir_reg<32>(d_jobs, n_jobs, cols, d_tw, boundary, d_out, stream);
+            case 40: return launch_iir_reg<40>(d_jobs, n_jobs, cols, d_tw, boundary, d_out, stream);
+            case 48: return launch_iir_reg<48>(d_jobs, n_jobs, cols, d_tw, boundary, d_out, stream);
+            case 56: return launch_iir_reg<56>(d_jobs, n_jobs, cols, d_tw, boundary, d_out, stream);
+            case 64: return launch_iir_reg<64>(d_jobs, n_jobs, cols, d_tw, boundary, d_out, stream);
+        }
+        return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_iir_block, dim3((cols + 63) / 64, n_jobs), dim3(64 * kIirChunks), 0, stream, d_jobs, d_tw,
+                       boundary, d_out);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_iir(const float* d_image, int64_t stride, int H, int W, int boundary, float* d_fT,
-                      const IirJob* d_hjobs, int n_hjobs, float2* d_JT, float2* d_J, const IirJob* d_vjobs, int n_vjobs,
-                      const float2* d_tw, float2* d_out, hipStream_t stream)
+                      const IirJob* d_hjobs, int n_hjobs, int max_lc_h, bool reg_h, float2* d_JT, float2* d_J,
+                      const IirJob* d_vjobs, int n_vjobs, int max_lc_v, bool reg_v, const float2* d_tw,
+                      float2* d_out, hipStream_t stream)
 {
     if (n_hjobs <= 0 || n_vjobs <= 0 || n_hjobs > 65535 || n_vjobs > 65535) return hipErrorInvalidValue;
     hipError_t e;
@@ -207,16 +413,13 @@ hipError_t launch_iir(const float* d_image, int64_t stride, int H, int W, int bo
                        stream, d_image, stride, H, W, d_fT);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // horizontal pass on the transposed image: lines of length W, H columns
-    hipLaunchKernelGGL(k_iir_block, dim3((H + 63) / 64, n_hjobs), dim3(64 * kIirChunks), 0, stream, d_hjobs, d_tw,
-                       boundary, (float2*)nullptr);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_iir_pass(d_hjobs, n_hjobs, H, max_lc_h, reg_h, d_tw, boundary, nullptr, stream)) != hipSuccess)
+        return e;
     hipLaunchKernelGGL(k_transpose_c64, dim3((H + kTile - 1) / kTile, (W + kTile - 1) / kTile, n_hjobs),
                        dim3(kTile, 8), 0, stream, (const float2*)d_JT, W, H, d_J);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // vertical pass: lines of length H, W columns, into the output channels
-    hipLaunchKernelGGL(k_iir_block, dim3((W + 63) / 64, n_vjobs), dim3(64 * kIirChunks), 0, stream, d_vjobs, d_tw,
-                       boundary, d_out);
-    return hipGetLastError();
+    return launch_iir_pass(d_vjobs, n_vjobs, W, max_lc_v, reg_v, d_tw, boundary, d_out, stream);
 }
 
 }  // namespace gabor

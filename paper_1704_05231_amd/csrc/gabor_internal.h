@@ -239,21 +239,31 @@ hipError_t launch_adjoint(const float2* d_G, int H, int W, int off, const AdjJob
 constexpr int kIirChunks = 16;
 struct IirJob {
     const void* in;            // float [n][in_stride] or float2 [n][in_stride]
-    float2* scratch;           // [n + 2T][cols] forward results
+    float2* scratch;           // [n + 2T][cols] forward results (scratch-plane kernel)
     float2* out;               // [n][out_stride], or null: out_base plane out_plane
     int64_t in_stride, out_stride;
     int32_t in_complex, conj;  // input type; conjugate a complex input
     int32_t n, cols, T, tw_off, out_plane;
-    int32_t lc;                // chunk length: ceil((n + 2T) / kIirChunks)
+    int32_t lc;                // chunk length: ceil((n + 2T) / chunks per line)
     float a[4];                // w[m] = a0 u[m] - a1 w[m-1] - a2 w[m-2] - a3 w[m-3]
     double apow[9];            // A^lc, row-major, A = [[-a1, -a2, -a3], [1, 0, 0], [0, 1, 0]]
+    double apow2[5][9];        // (A^lc)^(2^k), k = 1..5 (the register kernel's parallel carry)
 };
+// The register-resident recursion cuts each line into kIirRegChunks chunks
+// of at most kIirRegMaxChunk samples (lines of up to 4096 extended samples);
+// longer lines keep their forward results in a scratch plane (kIirChunks
+// chunks per line).
+constexpr int kIirRegChunks = 64;
+constexpr int kIirRegMaxChunk = 64;
 // Transpose, horizontal jobs (on the transposed image, into d_JT planes
 // [W][H]), transpose back into d_J planes [H][W], vertical jobs (into the
-// output channels of d_out).
+// output channels of d_out).  max_lc_h / max_lc_v: the longest chunk of each
+// pass's jobs; reg_h / reg_v: the pass's jobs are chunked for the register
+// kernel (else for the scratch-plane one).
 hipError_t launch_iir(const float* d_image, int64_t stride, int H, int W, int boundary, float* d_fT,
-                      const IirJob* d_hjobs, int n_hjobs, float2* d_JT, float2* d_J, const IirJob* d_vjobs, int n_vjobs,
-                      const float2* d_tw, float2* d_out, hipStream_t stream);
+                      const IirJob* d_hjobs, int n_hjobs, int max_lc_h, bool reg_h, float2* d_JT, float2* d_J,
+                      const IirJob* d_vjobs, int n_vjobs, int max_lc_v, bool reg_v, const float2* d_tw,
+                      float2* d_out, hipStream_t stream);
 
 // Launchers (defined in gabor_fp32.hip).  They return the status of the
 // launch (hipGetLastError after enqueue).

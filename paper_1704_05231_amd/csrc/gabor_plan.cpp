@@ -10,6 +10,7 @@
 //   - vertical jobs: one per horizontal result, producing theta and, when
 //     present, its partner pi - theta from the same J (Eq. (15)-(16)).
 #include <algorithm>
+#include <array>
 #include <complex>
 #include <cmath>
 #include <cstdlib>
@@ -602,9 +603,9 @@ extern "C" gabor_status gabor_bank_plan_iir(gabor_plan* out, int32_t height, int
     // Chunk length of a line of n + 2T samples and the state map across a
     // whole chunk, A^lc, in FP64 (A is the companion matrix of the
     // recursion acting on the state (w[m], w[m-1], w[m-2])).
-    auto set_chunks = [](IirJob& j, const double* a) {
+    auto set_chunks = [](IirJob& j, const double* a, int chunks, int lc) {
         const int ext = j.n + 2 * j.T;
-        j.lc = (ext + kIirChunks - 1) / kIirChunks;
+        j.lc = lc > 0 ? lc : (ext + chunks - 1) / chunks;
         double P[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
         const double A[9] = {-a[1], -a[2], -a[3], 1, 0, 0, 0, 1, 0};
         for (int k = 0; k < j.lc; ++k) {
@@ -615,8 +616,16 @@ extern "C" gabor_status gabor_bank_plan_iir(gabor_plan* out, int32_t height, int
             for (int q = 0; q < 9; ++q) P[q] = Q[q];
         }
         for (int q = 0; q < 9; ++q) j.apow[q] = P[q];
+        for (int k = 0; k < 5; ++k) {                     // repeated squares of A^lc
+            double Q[9];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c)
+                    Q[3 * r + c] = P[3 * r] * P[c] + P[3 * r + 1] * P[3 + c] + P[3 * r + 2] * P[6 + c];
+            for (int q = 0; q < 9; ++q) P[q] = j.apow2[k][q] = Q[q];
+        }
     };
     std::vector<int> h_of_v;                                  // horizontal job feeding each vertical job
+    std::vector<std::array<double, 4>> h_coef, v_coef;        // recursion coefficients per job
     int64_t h_scr = 0, v_scr = 0;
     for (int i = 0; i < n_freq; ++i) {
         double a[4];
@@ -647,7 +656,7 @@ extern "C" gabor_status gabor_bank_plan_iir(gabor_plan* out, int32_t height, int
             h.out_stride = height;
             h.tw_off = (int)tw.size();
             for (int c = 0; c < 4; ++c) h.a[c] = (float)a[c];
-            set_chunks(h, a);
+            h_coef.push_back({a[0], a[1], a[2], a[3]});
             push_twiddles(tw, omega[i] * cs[n], width, T);
             h_scr += (int64_t)(width + 2 * T) * height;
             const int hidx = (int)hj.size();
@@ -666,7 +675,7 @@ extern "C" gabor_status gabor_bank_plan_iir(gabor_plan* out, int32_t height, int
                 v.tw_off = vtw;
                 v.out_plane = i * n_orient + (side ? partner : n);
                 for (int c = 0; c < 4; ++c) v.a[c] = (float)a[c];
-                set_chunks(v, a);
+                v_coef.push_back({a[0], a[1], a[2], a[3]});
                 v_scr += (int64_t)(height + 2 * T) * width;
                 vj.push_back(v);
                 h_of_v.push_back(hidx);
@@ -679,6 +688,29 @@ extern "C" gabor_status gabor_bank_plan_iir(gabor_plan* out, int32_t height, int
     }
     p->n_ihj = (int)hj.size();
     p->n_ivj = (int)vj.size();
+    // Chunking per pass: kIirRegChunks chunks for the register kernel when
+    // every chunk fits it, else kIirChunks for the scratch-plane kernel
+    // (which alone needs the scratch plane).
+    // The register kernel takes one chunk length for the whole pass (the
+    // longest line's, rounded up to a multiple of 8), every line padded in
+    // front to kIirRegChunks chunks of it.
+    auto chunk_pass = [&](std::vector<IirJob>& jobs, const std::vector<std::array<double, 4>>& coef, bool* reg,
+                          int32_t* max_lc) {
+        int longest = 0;
+        for (const IirJob& j : jobs) longest = std::max(longest, j.n + 2 * j.T);
+        const int lc = ((longest + kIirRegChunks - 1) / kIirRegChunks + 7) / 8 * 8;
+        *reg = lc <= kIirRegMaxChunk;
+        *max_lc = 0;
+        for (size_t k = 0; k < jobs.size(); ++k) {
+            if (*reg) set_chunks(jobs[k], coef[k].data(), kIirRegChunks, lc);
+            else set_chunks(jobs[k], coef[k].data(), kIirChunks, 0);
+            *max_lc = std::max(*max_lc, jobs[k].lc);
+        }
+    };
+    chunk_pass(hj, h_coef, &p->iir_reg_h, &p->iir_lc_h);
+    chunk_pass(vj, v_coef, &p->iir_reg_v, &p->iir_lc_v);
+    if (p->iir_reg_h) h_scr = 0;
+    if (p->iir_reg_v) v_scr = 0;
     const size_t scr = (size_t)std::max(h_scr, v_scr) * sizeof(float2);
     const size_t plane2 = (size_t)npix * sizeof(float2);
     p->workspace_bytes = (int64_t)(scr + 2 * hj.size() * plane2 + npix * sizeof(float) + tw.size() * sizeof(float2) +
@@ -687,7 +719,7 @@ extern "C" gabor_status gabor_bank_plan_iir(gabor_plan* out, int32_t height, int
         release(p);
         return GABOR_ERR_OUT_OF_MEMORY;
     }
-    hipError_t e = hipMalloc((void**)&p->d_iscr, scr);
+    hipError_t e = scr ? hipMalloc((void**)&p->d_iscr, scr) : hipSuccess;
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_iJT, hj.size() * plane2);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_iJ, hj.size() * plane2);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_ifT, npix * sizeof(float));
@@ -703,14 +735,14 @@ extern "C" gabor_status gabor_bank_plan_iir(gabor_plan* out, int32_t height, int
     int64_t off = 0;
     for (size_t j = 0; j < hj.size(); ++j) {
         hj[j].in = p->d_ifT;
-        hj[j].scratch = p->d_iscr + off;
+        hj[j].scratch = h_scr ? p->d_iscr + off : nullptr;
         hj[j].out = p->d_iJT + (int64_t)j * npix;
         off += (int64_t)(hj[j].n + 2 * hj[j].T) * hj[j].cols;
     }
     off = 0;
     for (size_t j = 0; j < vj.size(); ++j) {
         vj[j].in = p->d_iJ + (int64_t)h_of_v[j] * npix;
-        vj[j].scratch = p->d_iscr + off;
+        vj[j].scratch = v_scr ? p->d_iscr + off : nullptr;
         vj[j].out = nullptr;
         off += (int64_t)(vj[j].n + 2 * vj[j].T) * vj[j].cols;
     }
@@ -737,8 +769,9 @@ extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int
     if (p->iir) {
         const int64_t npix = (int64_t)p->H * p->W;
         LaunchTimer tm(p, stream, "iir_fp32", p->row_macs + p->col_macs, 4 * npix + 8 * (int64_t)p->O * p->N * npix);
-        return launch_iir(d_image, row_stride_elems, p->H, p->W, p->boundary, p->d_ifT, p->d_ihj, p->n_ihj, p->d_iJT,
-                          p->d_iJ, p->d_ivj, p->n_ivj, p->d_itw, (float2*)d_out, stream) == hipSuccess
+        return launch_iir(d_image, row_stride_elems, p->H, p->W, p->boundary, p->d_ifT, p->d_ihj, p->n_ihj,
+                          p->iir_lc_h, p->iir_reg_h, p->d_iJT, p->d_iJ, p->d_ivj, p->n_ivj, p->iir_lc_v, p->iir_reg_v,
+                          p->d_itw, (float2*)d_out, stream) == hipSuccess
                    ? GABOR_OK
                    : GABOR_ERR_DEVICE;
     }
