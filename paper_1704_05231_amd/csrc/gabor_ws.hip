@@ -29,6 +29,9 @@ namespace gabor {
 namespace {
 
 constexpr int kWSX = 64;           // strip width: four 16-column blocks
+// Cache policy of the output stores: non-temporal (the outputs are written
+// once and not read again by the kernel)
+constexpr int kStoreNT = 2;
 constexpr int kWThreads = 512;     // four row waves, then four column waves
 constexpr int kRowThreads = 256;
 
@@ -382,8 +385,8 @@ __device__ __forceinline__ void ws_body(const StreamArgs& a, const FusedJob& jb,
                     vb[0] = __builtin_bit_cast(int, p1 + p2);
                     vb[1] = __builtin_bit_cast(int, p3 - p4);
                 }
-                __builtin_amdgcn_raw_buffer_store_b64(va, out_a, (int)off, 0, 0);
-                if constexpr (!JR) __builtin_amdgcn_raw_buffer_store_b64(vb, out_b, (int)off, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b64(va, out_a, (int)off, 0, kStoreNT);
+                if constexpr (!JR) __builtin_amdgcn_raw_buffer_store_b64(vb, out_b, (int)off, 0, kStoreNT);
             }
         };
         lds_barrier();                                             // B1

@@ -33,6 +33,13 @@ CASES = [
     (70, 129, [0.7, 0.0], [3.0, 0.8], 7, None, "zero"),  # odd N, omega = 0, small sigma
     (48, 40, [1.1], [2.2], 5, [0.0, 0.4, math.pi - 0.4, 1.0, math.pi / 2], "mirror"),
     (96, 110, [math.pi / 16], [16.0], 4, None, "mirror"),
+    # rows beyond the register kernel's 4096 extended samples: the horizontal
+    # pass keeps its forward results in the scratch plane (16 rows: with 3
+    # the mirror-folded columns repeat every 4 rows and the sigma = 4
+    # vertical channels cancel to 1 % of the input, where a peak-relative
+    # bar measures the cancellation, not the recursion)
+    (16, 4300, [1.0, math.pi / 4], [1.5, 4.0], 4, None, "mirror"),
+    (2, 4200, [0.6], [2.0], 3, None, "zero"),
 ]
 
 
