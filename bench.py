@@ -11,8 +11,9 @@ Prints one JSON line.  ``value`` is complex outputs per second of the FP32
 form; the other arithmetic forms are reported beside it under ``forms``
 (bf16_split is the matrix-core form that meets the 1e-3 bar).  ``roofline``
 describes the launch that takes most of the FP32 step, timed live with HIP
-events that libgabor records on each launch's stream during the timed
-region, against the algorithmic work libgabor reports for that launch (the
+events that libgabor records on each launch's stream during a second timed
+region of the same steps (the step time is taken without those events),
+against the algorithmic work libgabor reports for that launch (the
 four frequencies' launches run concurrently, so this time includes sharing
 the chip); beside it, ``step`` is the whole step's algorithmic work over
 ``ms_per_step`` and ``isolated`` the same launch timed alone in a plan of its
@@ -128,15 +129,20 @@ def time_form(binding, wl, img_dev, form, steps, warmup, tune=True, seg_rows=Non
     for _ in range(warmup):
         bank(img_dev, out)
     torch.cuda.synchronize()
-    bank.profile(True)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     start.record()
     for _ in range(steps):
         bank(img_dev, out)
     stop.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / steps
+    # per-launch durations: a second timed region of the same steps with the
+    # library's events around every launch (they cost about 10 us per step,
+    # so the step time above is taken without them)
+    bank.profile(True)
+    for _ in range(steps):
+        bank(img_dev, out)
+    torch.cuda.synchronize()
     prof = bank.profile_read()
     bank.profile(False)
     info = bank.info

@@ -212,15 +212,10 @@ hipError_t launch_adjoint(const float2* d_G, int H, int W, int off, const AdjJob
     if (grad_stride < Wo) return hipErrorInvalidValue;
     const size_t row_lds = adj_row_lds_bytes(max_kp), col_lds = adj_col_lds_bytes(max_kp);
     if (row_lds > 160 * 1024 || col_lds > 160 * 1024) return hipErrorInvalidValue;
+    static LdsLimit row_lim, col_lim;
     hipError_t e;
-    if (row_lds > 64 * 1024 &&
-        (e = hipFuncSetAttribute((const void*)k_adj_row, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)row_lds)) != hipSuccess)
-        return e;
-    if (col_lds > 64 * 1024 &&
-        (e = hipFuncSetAttribute((const void*)k_adj_col, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)col_lds)) != hipSuccess)
-        return e;
+    if ((e = row_lim.ensure((const void*)k_adj_row, row_lds)) != hipSuccess) return e;
+    if ((e = col_lim.ensure((const void*)k_adj_col, col_lds)) != hipSuccess) return e;
     const int seg = kAdjRowThreads * kAdjRowP;
     hipLaunchKernelGGL(k_adj_row, dim3((Wo + seg - 1) / seg, H, n_jobs), dim3(kAdjRowThreads), row_lds, stream,
                        d_G, H, W, off, d_jobs, d_taps, d_J);

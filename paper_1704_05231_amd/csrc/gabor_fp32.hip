@@ -289,6 +289,9 @@ hipError_t launch_row_fp32_batch(const BatchImage* d_imgs, int n_images, int max
     return hipErrorInvalidValue;
 }
 
+// one limit for k_col_fp32, shared by both of its launchers
+static LdsLimit g_col_lim;
+
 hipError_t launch_col_fp32_batch(const BatchImage* d_imgs, int n_images, int max_h, int max_w, int boundary,
                                  const FreqDesc& fd, const ColJob* d_jobs, int n_jobs, const float* d_taps,
                                  float2* d_J, hipStream_t stream)
@@ -296,9 +299,8 @@ hipError_t launch_col_fp32_batch(const BatchImage* d_imgs, int n_images, int max
     if (n_jobs <= 0) return hipSuccess;
     if (n_images <= 0 || (long long)n_jobs * n_images > 65535) return hipErrorInvalidValue;
     const size_t lds = sizeof(float2) * (size_t)(kColTY + fd.Kp) * kColTX;
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_col_fp32,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    {
+        const hipError_t e = g_col_lim.ensure((const void*)k_col_fp32, lds);
         if (e != hipSuccess) return e;
     }
     dim3 grid((max_w + kColTX - 1) / kColTX, (max_h + kColTY - 1) / kColTY, n_jobs * n_images);
@@ -313,9 +315,8 @@ hipError_t launch_col_fp32(const float2* d_J, int H, int W, int boundary, const 
 {
     if (n_jobs <= 0) return hipSuccess;
     const size_t lds = sizeof(float2) * (size_t)(kColTY + fd.Kp) * kColTX;
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_col_fp32,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    {
+        const hipError_t e = g_col_lim.ensure((const void*)k_col_fp32, lds);
         if (e != hipSuccess) return e;
     }
     dim3 grid((W + kColTX - 1) / kColTX, (H + kColTY - 1) / kColTY, n_jobs);

@@ -562,9 +562,9 @@ template <int OP, int Q>
 hipError_t launch_bq(const BatchArgs& b, hipStream_t stream)
 {
     const size_t lds = stream_lds_bytes(OP, Q);
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_stream_batch<OP, Q>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    {
+        static LdsLimit lim;
+        const hipError_t e = lim.ensure((const void*)k_stream_batch<OP, Q>, lds);
         if (e != hipSuccess) return e;
     }
     // Resident capacity, found once per instantiation and device.
@@ -600,9 +600,9 @@ template <int OP, int Q>
 hipError_t launch_q(const StreamArgs& a, int n_blocks, hipStream_t stream)
 {
     const size_t lds = stream_lds_bytes(OP, Q);
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_stream<OP, Q>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    {
+        static LdsLimit lim;
+        const hipError_t e = lim.ensure((const void*)k_stream<OP, Q>, lds);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((k_stream<OP, Q>), dim3(n_blocks), dim3(kThreads), lds, stream, a);
@@ -613,9 +613,9 @@ template <int OP, int Q>
 hipError_t launch_lq(const StreamArgs& a, const LsdftTaps& t, int n_blocks, hipStream_t stream)
 {
     const size_t lds = stream_lds_bytes(OP, Q);
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_lsdft<OP, Q>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    {
+        static LdsLimit lim;
+        const hipError_t e = lim.ensure((const void*)k_lsdft<OP, Q>, lds);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((k_lsdft<OP, Q>), dim3(n_blocks), dim3(kThreads), lds, stream, a, t);
@@ -967,9 +967,9 @@ hipError_t launch_adj_q(const AdjStreamArgs& a, hipStream_t stream)
 {
     const size_t lds = adjoint_stream_lds_bytes(Q);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_adj_stream<Q>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
+    {
+        static LdsLimit lim;
+        const hipError_t e = lim.ensure((const void*)k_adj_stream<Q>, lds);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_adj_stream<Q>, dim3(a.n_jobs * a.n_xs * a.n_ys * (a.n_images > 1 ? a.n_images : 1)),

@@ -5,7 +5,32 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 namespace gabor {
+
+// Dynamic-LDS limit of one kernel, raised once per device and size: the
+// attribute persists, and setting it before every launch costs a driver call
+// on the host (a noticeable part of an apply's submission time).
+struct LdsLimit {
+    static constexpr int kDevices = 64;
+    std::atomic<int> bytes[kDevices] = {};
+    hipError_t ensure(const void* fn, size_t need)
+    {
+        if (need <= 64 * 1024) return hipSuccess;
+        int dev = -1;
+        if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevices)
+            return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
+        if (bytes[dev].load(std::memory_order_acquire) >= (int)need) return hipSuccess;
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
+        if (e == hipSuccess) {
+            int cur = bytes[dev].load(std::memory_order_relaxed);
+            while (cur < (int)need && !bytes[dev].compare_exchange_weak(cur, (int)need, std::memory_order_acq_rel)) {
+            }
+        }
+        return e;
+    }
+};
 
 // Tap blocks: every tap table is zero-padded to a multiple of this many taps.
 constexpr int kTapBlock = 4;

@@ -70,6 +70,8 @@ void release(gabor_plan p)
     for (void* q : {(void*)p->d_ihj, (void*)p->d_ivj, (void*)p->d_itw, (void*)p->d_ifT, (void*)p->d_iJT,
                     (void*)p->d_iJ, (void*)p->d_iscr})
         if (q) (void)hipFree(q);
+    clear_apply_graphs(p);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
     for (hipStream_t st : p->aux) (void)hipStreamDestroy(st);
     for (hipEvent_t e : p->fork_ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : p->join_ev) (void)hipEventDestroy(e);
@@ -245,6 +247,9 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
     p->N = n_orient;
     p->boundary = boundary;
     p->precision = precision;
+    // LIBGABOR_NO_GRAPH=1 submits every apply launch by launch (comparison
+    // and testing); the default replays a cached graph of the apply.
+    p->use_graphs = !env_flag("LIBGABOR_NO_GRAPH");
     // LIBGABOR_KERNEL=stream keeps every fused frequency on the four-wave
     // streaming kernel (comparison and testing); the default runs the
     // wave-specialised kernel wherever its quarter is built.
@@ -758,14 +763,13 @@ extern "C" gabor_status gabor_bank_plan_iir(gabor_plan* out, int32_t height, int
     return GABOR_OK;
 }
 
-extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int64_t row_stride_elems,
-                                         void* d_out, void* hip_stream)
+namespace {
+
+// Every launch of one apply on `stream` (fork to the plan's streams, join
+// back), arguments already checked.
+gabor_status apply_eager(gabor_plan p, const float* d_image, int64_t row_stride_elems, void* d_out,
+                         hipStream_t stream)
 {
-    if (!p || !d_image || !d_out) return GABOR_ERR_INVALID_ARG;
-    if (row_stride_elems < p->W) return GABOR_ERR_INVALID_ARG;
-    if (!p->fjobs.empty() && (int64_t)(p->H - 1) * row_stride_elems + p->W >= (int64_t(1) << 30))
-        return GABOR_ERR_UNSUPPORTED;   // image span past the 32-bit buffer offsets of the fused kernel
-    hipStream_t stream = (hipStream_t)hip_stream;
     if (p->iir) {
         const int64_t npix = (int64_t)p->H * p->W;
         LaunchTimer tm(p, stream, "iir_fp32", p->row_macs + p->col_macs, 4 * npix + 8 * (int64_t)p->O * p->N * npix);
@@ -817,6 +821,84 @@ extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int
     return GABOR_OK;
 }
 
+}  // namespace
+
+namespace gabor {
+
+void clear_apply_graphs(gabor_plan_s* p)
+{
+    for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+    p->graphs.clear();
+}
+
+}  // namespace gabor
+
+namespace {
+
+// The apply as a graph captured on the plan's capture stream (fork, joins and
+// launches become graph dependencies and nodes); null if capture fails.
+hipGraphExec_t capture_apply(gabor_plan p, const float* d_image, int64_t row_stride_elems, void* d_out)
+{
+    if (!p->cap && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
+        p->cap = nullptr;
+        return nullptr;
+    }
+    if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+    const gabor_status st = apply_eager(p, d_image, row_stride_elems, d_out, p->cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->cap, &graph);
+    if (st != GABOR_OK || e != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) exec = nullptr;
+    (void)hipGraphDestroy(graph);
+    return exec;
+}
+
+// Cached graphs per plan: the few buffer triples a caller alternates between.
+constexpr size_t kApplyGraphs = 4;
+
+}  // namespace
+
+extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int64_t row_stride_elems,
+                                         void* d_out, void* hip_stream)
+{
+    if (!p || !d_image || !d_out) return GABOR_ERR_INVALID_ARG;
+    if (row_stride_elems < p->W) return GABOR_ERR_INVALID_ARG;
+    if (!p->fjobs.empty() && (int64_t)(p->H - 1) * row_stride_elems + p->W >= (int64_t(1) << 30))
+        return GABOR_ERR_UNSUPPORTED;   // image span past the 32-bit buffer offsets of the fused kernel
+    hipStream_t stream = (hipStream_t)hip_stream;
+    // Submitting an apply launch by launch costs about 15 runtime calls on the
+    // host, as long as the GPU work of a 16-bit apply; a cached graph of it is
+    // one call.  Profiled applies (events per launch) and applies on a stream
+    // that is itself being captured go launch by launch.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (!p->use_graphs || p->prof || hipStreamIsCapturing(stream, &cs) != hipSuccess ||
+        cs != hipStreamCaptureStatusNone)
+        return apply_eager(p, d_image, row_stride_elems, d_out, stream);
+    std::vector<int> segs(p->launches.size());
+    for (size_t i = 0; i < segs.size(); ++i) segs[i] = p->launches[i].seg_rows;
+    for (size_t k = 0; k < p->graphs.size(); ++k) {
+        if (p->graphs[k].img == d_image && p->graphs[k].stride == row_stride_elems && p->graphs[k].out == d_out &&
+            p->graphs[k].segs == segs) {
+            if (k + 1 != p->graphs.size()) std::rotate(p->graphs.begin() + (long)k, p->graphs.begin() + (long)k + 1,
+                                                       p->graphs.end());   // most recent last
+            return hipGraphLaunch(p->graphs.back().exec, stream) == hipSuccess ? GABOR_OK : GABOR_ERR_DEVICE;
+        }
+    }
+    hipGraphExec_t exec = capture_apply(p, d_image, row_stride_elems, d_out);
+    if (!exec) return apply_eager(p, d_image, row_stride_elems, d_out, stream);
+    if (p->graphs.size() >= kApplyGraphs) {
+        (void)hipGraphExecDestroy(p->graphs.front().exec);
+        p->graphs.erase(p->graphs.begin());
+    }
+    p->graphs.push_back({d_image, row_stride_elems, d_out, std::move(segs), exec});
+    return hipGraphLaunch(exec, stream) == hipSuccess ? GABOR_OK : GABOR_ERR_DEVICE;
+}
+
 extern "C" gabor_status gabor_bank_apply_batched(gabor_plan p, const float* d_images, int32_t n_images,
                                                  int64_t image_stride_elems, int64_t row_stride_elems, void* d_out,
                                                  void* hip_stream)
@@ -832,9 +914,11 @@ extern "C" gabor_status gabor_bank_apply_batched(gabor_plan p, const float* d_im
     for (int i = 0; i < p->O; ++i) one_launch = one_launch && fused_on_ws(p, i);
     if (!one_launch) {
         // plans with two-pass or four-wave frequencies: one apply per image
+        // (launch by launch: each image's buffers differ)
+        if (!p->fjobs.empty() && span >= (int64_t(1) << 30)) return GABOR_ERR_UNSUPPORTED;
         for (int b = 0; b < n_images; ++b) {
-            const gabor_status st = gabor_bank_apply(p, d_images + b * image_stride_elems, row_stride_elems,
-                                                     static_cast<float2*>(d_out) + b * out_bstride, hip_stream);
+            const gabor_status st = apply_eager(p, d_images + b * image_stride_elems, row_stride_elems,
+                                                static_cast<float2*>(d_out) + b * out_bstride, stream);
             if (st != GABOR_OK) return st;
         }
         return GABOR_OK;

@@ -72,6 +72,18 @@ struct gabor_plan_s {
     // priority) joined back to the caller's stream with events.
     std::vector<hipStream_t> aux;
     std::vector<hipEvent_t> fork_ev, join_ev;
+    // Replayable graphs of whole applies, keyed by their buffers and the
+    // schedule (most recent last), captured on a plan-owned stream.
+    struct ApplyGraph {
+        const float* img;
+        int64_t stride;
+        void* out;
+        std::vector<int> segs;             // the segment heights it was captured with
+        hipGraphExec_t exec;
+    };
+    std::vector<ApplyGraph> graphs;
+    hipStream_t cap = nullptr;
+    bool use_graphs = true;
     // per-kernel timing
     bool prof = false;
     struct Pending { int kind; hipEvent_t a, b; };
@@ -82,6 +94,8 @@ struct gabor_plan_s {
 };
 
 namespace gabor {
+// Drops the plan's cached apply graphs (the schedule they hold changed).
+void clear_apply_graphs(gabor_plan_s* p);
 // Fused frequency i of the plan runs on the wave-specialised kernel.
 inline bool fused_on_ws(const gabor_plan_s* p, int i)
 {

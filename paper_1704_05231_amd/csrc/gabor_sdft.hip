@@ -240,10 +240,8 @@ extern "C" gabor_status sdft_box_apply(const float* d_image, int32_t height, int
     const size_t lds = (size_t)((width + m_x + 15) & ~15) * sizeof(double2) + (size_t)4 * 64 * kRun * sizeof(float2) +
                        (size_t)kSdftMaxM * (sizeof(int64_t) + sizeof(double2));
     hipStream_t stream = (hipStream_t)hip_stream;
-    if (lds > 64 * 1024 &&
-        hipFuncSetAttribute((const void*)k_sdft_box, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-            hipSuccess)
-        return GABOR_ERR_DEVICE;
+    static LdsLimit lim;
+    if (lim.ensure((const void*)k_sdft_box, lds) != hipSuccess) return GABOR_ERR_DEVICE;
     hipLaunchKernelGGL(k_sdft_box, dim3(height, m_y / 2 + 1), dim3(kSdftThreads), lds, stream, a);
     return hipGetLastError() == hipSuccess ? GABOR_OK : GABOR_ERR_DEVICE;
 }

@@ -466,9 +466,9 @@ hipError_t launch_ws_tiles_q(const WsTilesArgs& t, hipStream_t stream)
 {
     const size_t lds = WsShape<OP, Q>::lds_bytes;
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_ws_tiles<OP, Q>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    {
+        static LdsLimit lim;
+        const hipError_t e = lim.ensure((const void*)k_ws_tiles<OP, Q>, lds);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((k_ws_tiles<OP, Q>), dim3(t.n_tiles), dim3(kWThreads), lds, stream, t);
@@ -488,9 +488,9 @@ hipError_t launch_ws_q(const StreamArgs& a, int n_blocks, hipStream_t stream)
 {
     const size_t lds = WsShape<OP, Q>::lds_bytes;
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_ws<OP, Q>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
+    {
+        static LdsLimit lim;
+        const hipError_t e = lim.ensure((const void*)k_ws<OP, Q>, lds);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((k_ws<OP, Q>), dim3(n_blocks), dim3(kWThreads), lds, stream, a);
