@@ -202,9 +202,9 @@ def step_roofline(form, flops, nbytes, ms):
             "compute_frac": round(fc, 4), "flops_per_step": flops, "bytes_per_step": nbytes, "ms_per_step": ms}
 
 
-def launch_radius(name: str) -> int:
-    """Radius in a launch's profile name (..._r48 -> 48)."""
-    return int(name.rsplit("_r", 1)[1])
+def launch_radii(name: str) -> list[int]:
+    """Radii in a launch's profile name (ws_f32_r48 -> [48], ws_bf16_r12+24 -> [12, 24])."""
+    return [int(v) for v in name.rsplit("_r", 1)[1].split("_")[0].split("+")]
 
 
 def isolated_launch(binding, wl, img_dev, form, name, tuning, steps, warmup):
@@ -213,17 +213,17 @@ def isolated_launch(binding, wl, img_dev, form, name, tuning, steps, warmup):
     chip, against the same per-launch algorithmic work."""
     import torch
     H, W = img_dev.shape
-    R = launch_radius(name)
-    i = [int(math.ceil(wl.radius_sigmas * s - 1e-9)) for s in wl.sigmas].index(R)
+    radii = [int(math.ceil(wl.radius_sigmas * s - 1e-9)) for s in wl.sigmas]
+    idx = [radii.index(R) for R in launch_radii(name)]
     if form == "fp32_twopass":
         os.environ["LIBGABOR_ALGO"] = "twopass"
     try:
-        bank = binding.GaborBank(H, W, [wl.omegas[i]], [wl.sigmas[i]], wl.n_orient, None, wl.radius_sigmas,
-                                 wl.boundary, precision_of(form))
+        bank = binding.GaborBank(H, W, [wl.omegas[i] for i in idx], [wl.sigmas[i] for i in idx], wl.n_orient, None,
+                                 wl.radius_sigmas, wl.boundary, precision_of(form))
     finally:
         os.environ.pop("LIBGABOR_ALGO", None)
-    bank.tuning = [tuning[i]]
-    out = torch.empty((1, wl.n_orient, H, W), dtype=torch.complex64, device="cuda")
+    bank.tuning = [tuning[i] for i in idx]
+    out = torch.empty((len(idx), wl.n_orient, H, W), dtype=torch.complex64, device="cuda")
     for _ in range(warmup):
         bank(img_dev, out)
     torch.cuda.synchronize()
@@ -238,7 +238,7 @@ def isolated_launch(binding, wl, img_dev, form, name, tuning, steps, warmup):
     tflops, gbs = 2.0 * st["real_macs"] / avg_s / 1e12, st["bytes"] / avg_s / 1e9
     kind, peak_c = compute_peak(form, name)
     fc, fm = tflops / peak_c, gbs / PEAK_HBM_GBS
-    r = {"kernel": name, "launch_ms": round(avg_s * 1e3, 5), "segment_rows": tuning[i]}
+    r = {"kernel": name, "launch_ms": round(avg_s * 1e3, 5), "segment_rows": [tuning[i] for i in idx]}
     if fc >= fm:
         r.update({"bound": kind, "achieved": round(tflops, 3), "peak": peak_c, "unit": "TFLOP/s", "frac": round(fc, 4)})
     else:

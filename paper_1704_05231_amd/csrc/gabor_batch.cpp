@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "gabor_plan_impl.h"
@@ -27,6 +28,8 @@ struct BatchGroup {
     int q;
     int first_tile, n_tiles;
     int64_t weight;            // total tile steps, for ordering the launches
+    std::string name;          // profile name: kernel and the radii it covers
+    int64_t macs, bytes;       // algorithmic work of one launch
 };
 
 }  // namespace
@@ -138,6 +141,28 @@ extern "C" gabor_status gabor_batch_create(gabor_batch* out, gabor_plan p, int32
                         }
                 }
             }
+        // profile name and algorithmic work: the group's frequencies over
+        // every image, scaled from the plan's full-size figures
+        {
+            double macs = 0.0, bytes = 0.0;
+            std::string radii;
+            const double full = (double)p->H * p->W;
+            for (int f = 0; f < p->O; ++f) {
+                const FreqLaunch& fl = p->launches[f];
+                if (!fl.fused || fl.q != q) continue;
+                radii += (radii.empty() ? "" : "+") + std::to_string(p->freqs[f].R);
+                for (int i = 0; i < n_images; ++i) {
+                    const double frac = (double)heights[i] * widths[i] / full;
+                    macs += (double)fl.macs * frac;
+                    bytes += (double)fl.bytes * frac;
+                }
+            }
+            const bool ws = p->use_ws && ws_supported(p->fused_op, q);
+            g.name = std::string(ws ? kWsNames[p->fused_op] : kFusedNames[p->fused_op]) + "_r" + radii +
+                     (n_images > 1 ? "_x" + std::to_string(n_images) : std::string());
+            g.macs = (int64_t)(macs + 0.5);
+            g.bytes = (int64_t)(bytes + 0.5);
+        }
         std::stable_sort(tl.begin(), tl.end(), [](const auto& a, const auto& c) { return a.first > c.first; });
         if ((int64_t)tiles.size() + (int64_t)tl.size() > 0x7fffffffLL) {
             batch_release(b);
@@ -191,6 +216,7 @@ extern "C" gabor_status gabor_batch_apply(gabor_batch b, void* hip_stream)
     for (size_t j = 0; j < b->groups.size(); ++j) {
         const BatchGroup& g = b->groups[j];
         hipStream_t ls = (j == 0 || !fork) ? stream : p->aux[(j - 1) % n_aux];
+        LaunchTimer tm(p, ls, g.name, g.macs, g.bytes);
         if (p->use_ws && ws_supported(p->fused_op, g.q)) {
             // one workgroup per tile, tiles in decreasing cost
             WsTilesArgs t{};

@@ -78,58 +78,6 @@ void release(gabor_plan p)
     delete p;
 }
 
-hipEvent_t take_event(gabor_plan p)
-{
-    if (!p->event_pool.empty()) {
-        hipEvent_t e = p->event_pool.back();
-        p->event_pool.pop_back();
-        return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-}
-
-int kind_index(gabor_plan p, const std::string& name, int64_t macs, int64_t bytes)
-{
-    for (size_t i = 0; i < p->kind_names.size(); ++i)
-        if (p->kind_names[i] == name) return (int)i;
-    p->kind_names.push_back(name);
-    gabor_kernel_stat st{};
-    std::strncpy(st.name, name.c_str(), sizeof(st.name) - 1);
-    st.real_macs = macs;
-    st.bytes = bytes;
-    p->stats.push_back(st);
-    return (int)p->kind_names.size() - 1;
-}
-
-// Brackets one launch with events when profiling is on.
-struct LaunchTimer {
-    gabor_plan p;
-    hipStream_t s;
-    int kind = -1;
-    hipEvent_t a = nullptr, b = nullptr;
-    LaunchTimer(gabor_plan plan, hipStream_t stream, const std::string& name, int64_t macs, int64_t bytes,
-                bool enabled = true)
-        : p(plan), s(stream)
-    {
-        if (!p->prof || !enabled) return;
-        kind = kind_index(p, name, macs, bytes);
-        a = take_event(p);
-        b = take_event(p);
-        if (a && b && hipEventRecord(a, s) == hipSuccess) return;
-        if (a) p->event_pool.push_back(a);
-        if (b) p->event_pool.push_back(b);
-        a = b = nullptr;
-    }
-    ~LaunchTimer()
-    {
-        if (!a) return;
-        if (hipEventRecord(b, s) == hipSuccess) p->pending.push_back({kind, a, b});
-        else { p->event_pool.push_back(a); p->event_pool.push_back(b); }
-    }
-};
-
 struct RowPass {
     double wc;      // w cos(theta)
     bool real;      // wc == 0: J is real
@@ -191,6 +139,59 @@ std::vector<BatchFreq> batch_freq_table(const gabor_plan_s* p)
         bf.q = fl.q;
     }
     return freqs;
+}
+
+}  // namespace gabor
+
+namespace gabor {
+
+hipEvent_t take_event(gabor_plan p)
+{
+    if (!p->event_pool.empty()) {
+        hipEvent_t e = p->event_pool.back();
+        p->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int kind_index(gabor_plan p, const std::string& name, int64_t macs, int64_t bytes)
+{
+    for (size_t i = 0; i < p->kind_names.size(); ++i)
+        if (p->kind_names[i] == name) return (int)i;
+    p->kind_names.push_back(name);
+    gabor_kernel_stat st{};
+    std::strncpy(st.name, name.c_str(), sizeof(st.name) - 1);
+    st.real_macs = macs;
+    st.bytes = bytes;
+    p->stats.push_back(st);
+    return (int)p->kind_names.size() - 1;
+}
+
+LaunchTimer::LaunchTimer(gabor_plan plan, hipStream_t stream, const std::string& name, int64_t macs, int64_t bytes,
+                         bool enabled)
+    : p(plan), s(stream)
+{
+    if (!p->prof || !enabled) return;
+    kind = kind_index(p, name, macs, bytes);
+    a = take_event(p);
+    b = take_event(p);
+    if (a && b && hipEventRecord(a, s) == hipSuccess) return;
+    if (a) p->event_pool.push_back(a);
+    if (b) p->event_pool.push_back(b);
+    a = b = nullptr;
+}
+
+LaunchTimer::~LaunchTimer()
+{
+    if (!a) return;
+    if (hipEventRecord(b, s) == hipSuccess) p->pending.push_back({kind, a, b});
+    else {
+        p->event_pool.push_back(a);
+        p->event_pool.push_back(b);
+    }
 }
 
 }  // namespace gabor
@@ -827,7 +828,10 @@ namespace gabor {
 
 void clear_apply_graphs(gabor_plan_s* p)
 {
-    for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (auto& g : p->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.batch) (void)gabor_batch_destroy(g.batch);
+    }
     p->graphs.clear();
 }
 
@@ -835,16 +839,17 @@ void clear_apply_graphs(gabor_plan_s* p)
 
 namespace {
 
-// The apply as a graph captured on the plan's capture stream (fork, joins and
-// launches become graph dependencies and nodes); null if capture fails.
-hipGraphExec_t capture_apply(gabor_plan p, const float* d_image, int64_t row_stride_elems, void* d_out)
+// A graph of one batch apply, captured on the plan's capture stream (the
+// fork, joins and launches become graph dependencies and nodes); null if
+// capture fails.
+hipGraphExec_t capture_batch(gabor_plan p, gabor_batch batch)
 {
     if (!p->cap && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
         p->cap = nullptr;
         return nullptr;
     }
     if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
-    const gabor_status st = apply_eager(p, d_image, row_stride_elems, d_out, p->cap);
+    const gabor_status st = gabor_batch_apply(batch, p->cap);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(p->cap, &graph);
     if (st != GABOR_OK || e != hipSuccess || !graph) {
@@ -858,7 +863,7 @@ hipGraphExec_t capture_apply(gabor_plan p, const float* d_image, int64_t row_str
     return exec;
 }
 
-// Cached graphs per plan: the few buffer triples a caller alternates between.
+// Cached applies per plan: the few buffer triples a caller alternates between.
 constexpr size_t kApplyGraphs = 4;
 
 }  // namespace
@@ -871,32 +876,49 @@ extern "C" gabor_status gabor_bank_apply(gabor_plan p, const float* d_image, int
     if (!p->fjobs.empty() && (int64_t)(p->H - 1) * row_stride_elems + p->W >= (int64_t(1) << 30))
         return GABOR_ERR_UNSUPPORTED;   // image span past the 32-bit buffer offsets of the fused kernel
     hipStream_t stream = (hipStream_t)hip_stream;
-    // Submitting an apply launch by launch costs about 15 runtime calls on the
-    // host, as long as the GPU work of a 16-bit apply; a cached graph of it is
-    // one call.  Profiled applies (events per launch) and applies on a stream
-    // that is itself being captured go launch by launch.
+    // An apply runs as a one-image batch of the plan: one launch per operand
+    // quarter over a tile table sorted by decreasing cost (rather than one
+    // launch per frequency), replayed from a cached graph: submitting it
+    // launch by launch costs about 15 runtime calls on the host, as long as
+    // a 16-bit apply's GPU work, and the graph is one.  The batch and graph
+    // are built at the first apply on a (image, stride, output, schedule);
+    // building synchronises the stream.  Profiled applies run the batch
+    // launch by launch (events per launch); applies on a stream that is itself
+    // being captured, plans with two-pass frequencies (whose batches would hold
+    // J planes of their own) and recursive-smoother plans run the
+    // per-frequency launches directly.
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (!p->use_graphs || p->prof || hipStreamIsCapturing(stream, &cs) != hipSuccess ||
+    if (!p->use_graphs || p->iir || !p->row_groups.empty() || hipStreamIsCapturing(stream, &cs) != hipSuccess ||
         cs != hipStreamCaptureStatusNone)
         return apply_eager(p, d_image, row_stride_elems, d_out, stream);
     std::vector<int> segs(p->launches.size());
     for (size_t i = 0; i < segs.size(); ++i) segs[i] = p->launches[i].seg_rows;
-    for (size_t k = 0; k < p->graphs.size(); ++k) {
+    size_t k = 0;
+    for (; k < p->graphs.size(); ++k)
         if (p->graphs[k].img == d_image && p->graphs[k].stride == row_stride_elems && p->graphs[k].out == d_out &&
-            p->graphs[k].segs == segs) {
-            if (k + 1 != p->graphs.size()) std::rotate(p->graphs.begin() + (long)k, p->graphs.begin() + (long)k + 1,
-                                                       p->graphs.end());   // most recent last
-            return hipGraphLaunch(p->graphs.back().exec, stream) == hipSuccess ? GABOR_OK : GABOR_ERR_DEVICE;
+            p->graphs[k].segs == segs)
+            break;
+    if (k < p->graphs.size()) {
+        std::rotate(p->graphs.begin() + (long)k, p->graphs.begin() + (long)k + 1, p->graphs.end());  // most recent last
+    } else {
+        gabor_batch b = nullptr;
+        const int32_t h = p->H, w = p->W;
+        const float* const imgs[1] = {d_image};
+        void* const outs[1] = {d_out};
+        if (gabor_batch_create(&b, p, 1, imgs, &h, &w, &row_stride_elems, outs, hip_stream) != GABOR_OK)
+            return apply_eager(p, d_image, row_stride_elems, d_out, stream);
+        if (p->graphs.size() >= kApplyGraphs) {
+            if (p->graphs.front().exec) (void)hipGraphExecDestroy(p->graphs.front().exec);
+            (void)gabor_batch_destroy(p->graphs.front().batch);
+            p->graphs.erase(p->graphs.begin());
         }
+        p->graphs.push_back({d_image, row_stride_elems, d_out, std::move(segs), b, nullptr});
     }
-    hipGraphExec_t exec = capture_apply(p, d_image, row_stride_elems, d_out);
-    if (!exec) return apply_eager(p, d_image, row_stride_elems, d_out, stream);
-    if (p->graphs.size() >= kApplyGraphs) {
-        (void)hipGraphExecDestroy(p->graphs.front().exec);
-        p->graphs.erase(p->graphs.begin());
-    }
-    p->graphs.push_back({d_image, row_stride_elems, d_out, std::move(segs), exec});
-    return hipGraphLaunch(exec, stream) == hipSuccess ? GABOR_OK : GABOR_ERR_DEVICE;
+    auto& g = p->graphs.back();
+    if (p->prof) return gabor_batch_apply(g.batch, hip_stream);
+    if (!g.exec) g.exec = capture_batch(p, g.batch);
+    if (!g.exec) return gabor_batch_apply(g.batch, hip_stream);
+    return hipGraphLaunch(g.exec, stream) == hipSuccess ? GABOR_OK : GABOR_ERR_DEVICE;
 }
 
 extern "C" gabor_status gabor_bank_apply_batched(gabor_plan p, const float* d_images, int32_t n_images,

@@ -79,6 +79,7 @@ struct gabor_plan_s {
         int64_t stride;
         void* out;
         std::vector<int> segs;             // the segment heights it was captured with
+        gabor_batch batch;                 // the one-image batch it launches
         hipGraphExec_t exec;
     };
     std::vector<ApplyGraph> graphs;
@@ -94,8 +95,20 @@ struct gabor_plan_s {
 };
 
 namespace gabor {
-// Drops the plan's cached apply graphs (the schedule they hold changed).
+// Drops the plan's cached apply graphs and the batches they replay.
 void clear_apply_graphs(gabor_plan_s* p);
+// Brackets one launch with events on its stream while the plan's profiling
+// is on (gabor_profile_enable); the stat `name` holds one launch's
+// algorithmic work.
+struct LaunchTimer {
+    gabor_plan p;
+    hipStream_t s;
+    int kind = -1;
+    hipEvent_t a = nullptr, b = nullptr;
+    LaunchTimer(gabor_plan plan, hipStream_t stream, const std::string& name, int64_t macs, int64_t bytes,
+                bool enabled = true);
+    ~LaunchTimer();
+};
 // Fused frequency i of the plan runs on the wave-specialised kernel.
 inline bool fused_on_ws(const gabor_plan_s* p, int i)
 {
