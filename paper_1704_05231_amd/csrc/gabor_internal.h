@@ -191,6 +191,9 @@ struct LsdftTaps {
 constexpr int kWsMaxQuarter = 32;
 bool ws_supported(int op, int Q);
 hipError_t launch_ws(int op, const StreamArgs& a, int Q, hipStream_t stream);
+// Raises the dynamic-LDS limits of the wave-specialised kernels of (op, Q)
+// once, outside any graph capture (plan creation).
+hipError_t prepare_ws(int op, int Q);
 size_t ws_lds_bytes(int op, int Q);
 
 // The same kernel over a tile table (batches): workgroup b takes tile b,
@@ -219,10 +222,12 @@ template <int OP> hipError_t lsdft_form(const StreamArgs& a, const LsdftTaps& t,
 template <int OP> hipError_t batch_form(const BatchArgs& b, int Q, hipStream_t stream);
 template <int OP> hipError_t ws_form(const StreamArgs& a, int Q, int n_blocks, hipStream_t stream);
 template <int OP> hipError_t ws_tiles_form(const WsTilesArgs& t, int Q, hipStream_t stream);
+template <int OP> hipError_t ws_prepare_form(int Q);
 #define GABOR_DECLARE_FORM(OP)                                                                   \
     template <> hipError_t stream_form<OP>(const StreamArgs&, int, int, hipStream_t);            \
     template <> hipError_t ws_form<OP>(const StreamArgs&, int, int, hipStream_t);                \
     template <> hipError_t ws_tiles_form<OP>(const WsTilesArgs&, int, hipStream_t);              \
+    template <> hipError_t ws_prepare_form<OP>(int);                                              \
     template <> hipError_t lsdft_form<OP>(const StreamArgs&, const LsdftTaps&, int, int, hipStream_t); \
     template <> hipError_t batch_form<OP>(const BatchArgs&, int, hipStream_t);
 GABOR_DECLARE_FORM(FUSED_F32)

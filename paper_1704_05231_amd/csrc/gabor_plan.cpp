@@ -504,6 +504,13 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
         release(p);
         return GABOR_ERR_DEVICE;
     }
+    // Kernel attributes of the wave-specialised launches, set now rather than
+    // inside a graph capture of a later apply.
+    for (int i = 0; i < p->O; ++i)
+        if (fused_on_ws(p, i) && prepare_ws(p->fused_op, p->launches[i].q) != hipSuccess) {
+            release(p);
+            return GABOR_ERR_DEVICE;
+        }
     // Independent frequencies run concurrently: up to three auxiliary
     // streams beside the caller's (four hardware queues).
     const int n_conc = std::min<int>(3, (int)p->order.size() - 1);

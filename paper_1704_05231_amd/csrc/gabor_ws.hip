@@ -461,14 +461,20 @@ __global__ __launch_bounds__(kWThreads) void k_ws_tiles(WsTilesArgs t)
     else ws_body<OP, Q, false, false>(a, jb, tl.rest);
 }
 
+// Dynamic-LDS limits of the two kernels of one form and quarter (raised at
+// plan creation, so that no launch captured in a graph needs to).
+template <int OP, int Q>
+LdsLimit ws_tiles_limit;
+template <int OP, int Q>
+LdsLimit ws_limit;
+
 template <int OP, int Q>
 hipError_t launch_ws_tiles_q(const WsTilesArgs& t, hipStream_t stream)
 {
     const size_t lds = WsShape<OP, Q>::lds_bytes;
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     {
-        static LdsLimit lim;
-        const hipError_t e = lim.ensure((const void*)k_ws_tiles<OP, Q>, lds);
+        const hipError_t e = ws_tiles_limit<OP, Q>.ensure((const void*)k_ws_tiles<OP, Q>, lds);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((k_ws_tiles<OP, Q>), dim3(t.n_tiles), dim3(kWThreads), lds, stream, t);
@@ -489,12 +495,29 @@ hipError_t launch_ws_q(const StreamArgs& a, int n_blocks, hipStream_t stream)
     const size_t lds = WsShape<OP, Q>::lds_bytes;
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     {
-        static LdsLimit lim;
-        const hipError_t e = lim.ensure((const void*)k_ws<OP, Q>, lds);
+        const hipError_t e = ws_limit<OP, Q>.ensure((const void*)k_ws<OP, Q>, lds);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((k_ws<OP, Q>), dim3(n_blocks), dim3(kWThreads), lds, stream, a);
     return hipGetLastError();
+}
+
+template <int OP, int Q>
+hipError_t prepare_ws_q()
+{
+    const size_t lds = WsShape<OP, Q>::lds_bytes;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipError_t e = ws_limit<OP, Q>.ensure((const void*)k_ws<OP, Q>, lds);
+    if (e == hipSuccess) e = ws_tiles_limit<OP, Q>.ensure((const void*)k_ws_tiles<OP, Q>, lds);
+    return e;
+}
+
+template <int OP, int... Qs>
+hipError_t prepare_ws_list(int Q)
+{
+    hipError_t e = hipErrorInvalidValue;
+    ((Q == Qs ? (void)(e = prepare_ws_q<OP, Qs>()) : (void)0), ...);
+    return e;
 }
 
 template <int OP, int... Qs>
@@ -518,6 +541,15 @@ hipError_t ws_form<GABOR_FORM>(const StreamArgs& a, int Q, int n_blocks, hipStre
         return launch_ws_list<GABOR_FORM, 4, 8, 12, 16, 20, 24, 28, 32>(a, Q, n_blocks, stream);
     else
         return launch_ws_list<GABOR_FORM, 8, 16, 24, 32>(a, Q, n_blocks, stream);
+}
+
+template <>
+hipError_t ws_prepare_form<GABOR_FORM>(int Q)
+{
+    if constexpr (GABOR_FORM == FUSED_F32)
+        return prepare_ws_list<GABOR_FORM, 4, 8, 12, 16, 20, 24, 28, 32>(Q);
+    else
+        return prepare_ws_list<GABOR_FORM, 8, 16, 24, 32>(Q);
 }
 
 template <>
@@ -553,6 +585,19 @@ hipError_t launch_ws_tiles(int op, const WsTilesArgs& t, int Q, hipStream_t stre
         case FUSED_BF16X3: return ws_tiles_form<FUSED_BF16X3>(t, Q, stream);
         case FUSED_F16: return ws_tiles_form<FUSED_F16>(t, Q, stream);
         case FUSED_F16X3: return ws_tiles_form<FUSED_F16X3>(t, Q, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t prepare_ws(int op, int Q)
+{
+    if (!ws_supported(op, Q)) return hipErrorInvalidValue;
+    switch (op) {
+        case FUSED_F32: return ws_prepare_form<FUSED_F32>(Q);
+        case FUSED_BF16: return ws_prepare_form<FUSED_BF16>(Q);
+        case FUSED_BF16X3: return ws_prepare_form<FUSED_BF16X3>(Q);
+        case FUSED_F16: return ws_prepare_form<FUSED_F16>(Q);
+        case FUSED_F16X3: return ws_prepare_form<FUSED_F16X3>(Q);
     }
     return hipErrorInvalidValue;
 }
