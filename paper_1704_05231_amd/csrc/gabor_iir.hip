@@ -7,8 +7,9 @@
 // Every recursion runs down the columns of a plane, one lane per column
 // (coalesced across the wave), each line cut into chunks that the waves of a
 // workgroup process in parallel (block-parallel linear recursion); the
-// horizontal pass therefore works on the transposed image and its result is
-// transposed back.  Each line is extended
+// horizontal pass therefore works on the transposed image, and writes its
+// result back as rows (staged through LDS) or, for long lines, into a
+// transposed plane that a transpose turns back.  Each line is extended
 // by T samples on both sides by the boundary rule and the recursion starts
 // from rest at the far end of the extension; the forward results of the
 // whole extended line are kept in a scratch plane for the backward pass.
@@ -208,7 +209,7 @@ __global__ __launch_bounds__(64 * kIirChunks) void k_iir_block(const IirJob* __r
 // the zero-input response of its entering state (the recursion is linear),
 // so nothing is rerun from the input; likewise backward.
 constexpr int kIirRegCols = 512 / kIirRegChunks;
-template <int LC>
+template <int LC, bool ROWS>
 __global__ __launch_bounds__(512) void k_iir_reg(const IirJob* __restrict__ jobs, const float2* __restrict__ tw,
                                                  int boundary, float2* __restrict__ out_base)
 {
@@ -218,7 +219,8 @@ __global__ __launch_bounds__(512) void k_iir_reg(const IirJob* __restrict__ jobs
     const IirJob jb = jobs[blockIdx.y];
     const int lane = threadIdx.x & 63;
     const int cl = lane % NC, chunk = (64 / NC) * (threadIdx.x >> 6) + lane / NC;
-    const int col = blockIdx.x * NC + cl;
+    const int xb = blockIdx.x;
+    const int col = xb * NC + cl;
     const bool live = col < jb.cols;
     const int n = jb.n, T = jb.T, ext = n + 2 * T;
     constexpr int lc = LC;                                         // the host sets jb.lc = LC
@@ -353,10 +355,50 @@ __global__ __launch_bounds__(512) void k_iir_reg(const IirJob* __restrict__ jobs
 #pragma unroll
     for (int k = LC - 1; k >= 0; --k) buf[k] = rec(buf[k], w1, w2, w3);
     carry(false, w1, w2, w3);
-    // entering-state response, then demodulate the image samples
-    float2* out = (jb.out ? jb.out : out_base + (int64_t)jb.out_plane * n * jb.cols) + col;
+    float2* const base = jb.out ? jb.out : out_base + (int64_t)jb.out_plane * n * jb.cols;
+    if constexpr (ROWS) {
+        // The lines leave as rows, through the carry buffer (free after the
+        // last scan): each round stages CPR chunks of all NC lines, written by
+        // the waves that hold them, then wave i stores line i's segment with
+        // contiguous lanes.
+        constexpr int CAP = (int)(sizeof(sc) / sizeof(float2)) / (NC * LC);   // chunks that fit
+        constexpr int CPR = CAP >= 64 ? 64 : CAP >= 32 ? 32 : CAP >= 16 ? 16 : 8;
+        static_assert(LC <= kIirRowChunk && NC == 8 && CPR % (64 / NC) == 0 && CH % CPR == 0,
+                      "whole waves per round, one line per wave");
+        constexpr int SEG = CPR * LC;
+        float2* stage = reinterpret_cast<float2*>(&sc[0][0][0]);
 #pragma unroll
-    for (int k = LC - 1; k >= 0; --k) {
+        for (int k = LC - 1; k >= 0; --k) {
+            const float2 h = hom(w1, w2, w3);
+            const float2 v = make_float2(buf[k].x + h.x, buf[k].y + h.y);
+            const float2 t = tws[max(m0 + k, 0)];
+            buf[k] = make_float2(v.x * t.x - v.y * t.y, v.x * t.y + v.y * t.x);
+        }
+        const int wave = threadIdx.x >> 6;
+        for (int r = 0; r < CH / CPR; ++r) {
+            const int mstart = ext - (CH - r * CPR) * lc;           // first extended sample of the round
+            if (chunk / CPR == r) {
+                // every sample of the chunk (padding and extension too: only
+                // the image's samples are copied out below)
+                float2* st = stage + cl * SEG + (m0 - mstart);
+#pragma unroll
+                for (int k = 0; k < LC; ++k) st[k] = buf[k];
+            }
+            __syncthreads();
+            const int y = xb * NC + wave;                             // line of this wave
+            const int lo = max(0, mstart - T), hi = min(n, mstart + SEG - T);
+            if (y < jb.cols) {
+                float2* row = base + (int64_t)y * jb.out_stride;
+                const float2* src = stage + wave * SEG + (T - mstart);
+                for (int l = lo + lane; l < hi; l += 64) row[l] = src[l];
+            }
+            __syncthreads();
+        }
+    } else {
+        // entering-state response, then demodulate the image samples
+        float2* out = base + col;
+#pragma unroll
+        for (int k = LC - 1; k >= 0; --k) {
             const float2 h = hom(w1, w2, w3);
             const float2 v = make_float2(buf[k].x + h.x, buf[k].y + h.y);
             const int l = m0 + k - T;
@@ -365,22 +407,36 @@ __global__ __launch_bounds__(512) void k_iir_reg(const IirJob* __restrict__ jobs
                 out[(int64_t)l * jb.out_stride] = make_float2(v.x * t.x - v.y * t.y, v.x * t.y + v.y * t.x);
             }
         }
+    }
 }
 
-template <int LC>
+template <int LC, bool ROWS = false>
 hipError_t launch_iir_reg(const IirJob* d_jobs, int n_jobs, int cols, const float2* d_tw, int boundary,
                           float2* d_out, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_iir_reg<LC>, dim3((cols + kIirRegCols - 1) / kIirRegCols, n_jobs), dim3(512), 0, stream,
+    hipLaunchKernelGGL((k_iir_reg<LC, ROWS>), dim3((cols + kIirRegCols - 1) / kIirRegCols, n_jobs), dim3(512), 0, stream,
                        d_jobs, d_tw, boundary, d_out);
     return hipGetLastError();
 }
 
 // One pass: the register kernel when the jobs' chunks (of kIirRegChunks per
 // line) fit, else the scratch-plane one (kIirChunks per line).
-hipError_t launch_iir_pass(const IirJob* d_jobs, int n_jobs, int cols, int max_lc, bool reg, const float2* d_tw,
-                           int boundary, float2* d_out, hipStream_t stream)
+hipError_t launch_iir_pass(const IirJob* d_jobs, int n_jobs, int cols, int max_lc, bool reg, bool rows,
+                           const float2* d_tw, int boundary, float2* d_out, hipStream_t stream)
 {
+    if (reg && rows) {
+        // every job writes its lines as rows (max_lc <= kIirRowChunk)
+        switch (max_lc) {
+            case 8: return launch_iir_reg<8, true>(d_jobs, n_jobs, cols, d_tw, boundary, d_out, stream);
+            case 16: return launch_iir_reg<16, true>(d_jobs, n_jobs, cols, d_tw, boundary, d_out, stream);
+            case 24: return launch_iir_reg<24, true>(d_jobs, n_jobs, cols, d_tw, boundary, d_out, stream);
+            case 32: return launch_iir_reg<32, true>(d_jobs, n_jobs, cols, d_tw, boundary, d_out, stream);
+            case 40: return launch_iir_reg<40, true>(d_jobs, n_jobs, cols, d_tw, boundary, d_out, stream);
+            case 48: return launch_iir_reg<48, true>(d_jobs, n_jobs, cols, d_tw, boundary, d_out, stream);
+        }
+        return hipErrorInvalidValue;
+    }
+    if (rows) return hipErrorInvalidValue;
     if (reg) {
         // every job of the pass has lc = max_lc, a multiple of 8 from 8 to 64
         switch (max_lc) {
@@ -403,7 +459,7 @@ hipError_t launch_iir_pass(const IirJob* d_jobs, int n_jobs, int cols, int max_l
 }  // namespace
 
 hipError_t launch_iir(const float* d_image, int64_t stride, int H, int W, int boundary, float* d_fT,
-                      const IirJob* d_hjobs, int n_hjobs, int max_lc_h, bool reg_h, float2* d_JT, float2* d_J,
+                      const IirJob* d_hjobs, int n_hjobs, int max_lc_h, bool reg_h, bool rows_h, float2* d_JT, float2* d_J,
                       const IirJob* d_vjobs, int n_vjobs, int max_lc_v, bool reg_v, const float2* d_tw,
                       float2* d_out, hipStream_t stream)
 {
@@ -413,13 +469,16 @@ hipError_t launch_iir(const float* d_image, int64_t stride, int H, int W, int bo
                        stream, d_image, stride, H, W, d_fT);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // horizontal pass on the transposed image: lines of length W, H columns
-    if ((e = launch_iir_pass(d_hjobs, n_hjobs, H, max_lc_h, reg_h, d_tw, boundary, nullptr, stream)) != hipSuccess)
+    if ((e = launch_iir_pass(d_hjobs, n_hjobs, H, max_lc_h, reg_h, rows_h, d_tw, boundary, nullptr, stream)) !=
+        hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_transpose_c64, dim3((H + kTile - 1) / kTile, (W + kTile - 1) / kTile, n_hjobs),
-                       dim3(kTile, 8), 0, stream, (const float2*)d_JT, W, H, d_J);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!rows_h) {
+        hipLaunchKernelGGL(k_transpose_c64, dim3((H + kTile - 1) / kTile, (W + kTile - 1) / kTile, n_hjobs),
+                           dim3(kTile, 8), 0, stream, (const float2*)d_JT, W, H, d_J);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     // vertical pass: lines of length H, W columns, into the output channels
-    return launch_iir_pass(d_vjobs, n_vjobs, W, max_lc_v, reg_v, d_tw, boundary, d_out, stream);
+    return launch_iir_pass(d_vjobs, n_vjobs, W, max_lc_v, reg_v, false, d_tw, boundary, d_out, stream);
 }
 
 }  // namespace gabor

@@ -274,6 +274,7 @@ struct IirJob {
     int64_t in_stride, out_stride;
     int32_t in_complex, conj;  // input type; conjugate a complex input
     int32_t n, cols, T, tw_off, out_plane;
+    int32_t out_rows;          // line c's outputs go to row c of the output (register kernel, lc <= kIirRowChunk)
     int32_t lc;                // chunk length: ceil((n + 2T) / chunks per line)
     float a[4];                // w[m] = a0 u[m] - a1 w[m-1] - a2 w[m-2] - a3 w[m-3]
     double apow[9];            // A^lc, row-major, A = [[-a1, -a2, -a3], [1, 0, 0], [0, 1, 0]]
@@ -285,13 +286,17 @@ struct IirJob {
 // chunks per line).
 constexpr int kIirRegChunks = 64;
 constexpr int kIirRegMaxChunk = 64;
-// Transpose, horizontal jobs (on the transposed image, into d_JT planes
-// [W][H]), transpose back into d_J planes [H][W], vertical jobs (into the
-// output channels of d_out).  max_lc_h / max_lc_v: the longest chunk of each
-// pass's jobs; reg_h / reg_v: the pass's jobs are chunked for the register
-// kernel (else for the scratch-plane one).
+// Longest chunk with which the register kernel can write its lines as rows
+// (staged through its 24 KB carry buffer, eight chunks of each line at a time).
+constexpr int kIirRowChunk = 48;
+// Transpose, horizontal jobs (on the transposed image, into d_J planes [H][W]
+// directly when their jobs write rows, else into d_JT planes [W][H] and
+// transposed back into d_J), vertical jobs (into the output channels of
+// d_out).  max_lc_h / max_lc_v: the longest chunk of each pass's jobs;
+// reg_h / reg_v: the pass's jobs are chunked for the register kernel (else
+// for the scratch-plane one); rows_h: the horizontal jobs write rows.
 hipError_t launch_iir(const float* d_image, int64_t stride, int H, int W, int boundary, float* d_fT,
-                      const IirJob* d_hjobs, int n_hjobs, int max_lc_h, bool reg_h, float2* d_JT, float2* d_J,
+                      const IirJob* d_hjobs, int n_hjobs, int max_lc_h, bool reg_h, bool rows_h, float2* d_JT, float2* d_J,
                       const IirJob* d_vjobs, int n_vjobs, int max_lc_v, bool reg_v, const float2* d_tw,
                       float2* d_out, hipStream_t stream);
 

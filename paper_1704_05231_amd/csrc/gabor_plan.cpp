@@ -724,16 +724,18 @@ extern "C" gabor_status gabor_bank_plan_iir(gabor_plan* out, int32_t height, int
     chunk_pass(vj, v_coef, &p->iir_reg_v, &p->iir_lc_v);
     if (p->iir_reg_h) h_scr = 0;
     if (p->iir_reg_v) v_scr = 0;
+    p->iir_rows_h = p->iir_reg_h && p->iir_lc_h <= kIirRowChunk;
     const size_t scr = (size_t)std::max(h_scr, v_scr) * sizeof(float2);
     const size_t plane2 = (size_t)npix * sizeof(float2);
-    p->workspace_bytes = (int64_t)(scr + 2 * hj.size() * plane2 + npix * sizeof(float) + tw.size() * sizeof(float2) +
-                                   (hj.size() + vj.size()) * sizeof(IirJob));
+    const size_t jt_bytes = p->iir_rows_h ? 0 : hj.size() * plane2;
+    p->workspace_bytes = (int64_t)(scr + jt_bytes + hj.size() * plane2 + npix * sizeof(float) +
+                                   tw.size() * sizeof(float2) + (hj.size() + vj.size()) * sizeof(IirJob));
     if (env_flag("LIBGABOR_FAIL_ALLOC")) {
         release(p);
         return GABOR_ERR_OUT_OF_MEMORY;
     }
     hipError_t e = scr ? hipMalloc((void**)&p->d_iscr, scr) : hipSuccess;
-    if (e == hipSuccess) e = hipMalloc((void**)&p->d_iJT, hj.size() * plane2);
+    if (e == hipSuccess && jt_bytes) e = hipMalloc((void**)&p->d_iJT, jt_bytes);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_iJ, hj.size() * plane2);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_ifT, npix * sizeof(float));
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_itw, tw.size() * sizeof(float2));
@@ -743,13 +745,19 @@ extern "C" gabor_status gabor_bank_plan_iir(gabor_plan* out, int32_t height, int
         release(p);
         return e == hipErrorOutOfMemory ? GABOR_ERR_OUT_OF_MEMORY : GABOR_ERR_DEVICE;
     }
-    // device pointers of the job tables: scratch slices, transposed and
-    // straight J planes
+    // device pointers of the job tables: scratch slices, J planes (written
+    // as rows, or transposed and turned back)
     int64_t off = 0;
     for (size_t j = 0; j < hj.size(); ++j) {
         hj[j].in = p->d_ifT;
         hj[j].scratch = h_scr ? p->d_iscr + off : nullptr;
-        hj[j].out = p->d_iJT + (int64_t)j * npix;
+        if (p->iir_rows_h) {
+            hj[j].out = p->d_iJ + (int64_t)j * npix;
+            hj[j].out_rows = 1;
+            hj[j].out_stride = width;
+        } else {
+            hj[j].out = p->d_iJT + (int64_t)j * npix;
+        }
         off += (int64_t)(hj[j].n + 2 * hj[j].T) * hj[j].cols;
     }
     off = 0;
@@ -782,7 +790,7 @@ gabor_status apply_eager(gabor_plan p, const float* d_image, int64_t row_stride_
         const int64_t npix = (int64_t)p->H * p->W;
         LaunchTimer tm(p, stream, "iir_fp32", p->row_macs + p->col_macs, 4 * npix + 8 * (int64_t)p->O * p->N * npix);
         return launch_iir(d_image, row_stride_elems, p->H, p->W, p->boundary, p->d_ifT, p->d_ihj, p->n_ihj,
-                          p->iir_lc_h, p->iir_reg_h, p->d_iJT, p->d_iJ, p->d_ivj, p->n_ivj, p->iir_lc_v, p->iir_reg_v,
+                          p->iir_lc_h, p->iir_reg_h, p->iir_rows_h, p->d_iJT, p->d_iJ, p->d_ivj, p->n_ivj, p->iir_lc_v, p->iir_reg_v,
                           p->d_itw, (float2*)d_out, stream) == hipSuccess
                    ? GABOR_OK
                    : GABOR_ERR_DEVICE;

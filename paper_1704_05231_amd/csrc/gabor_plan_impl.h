@@ -51,6 +51,7 @@ struct gabor_plan_s {
     int32_t n_ihj = 0, n_ivj = 0;
     int32_t iir_lc_h = 0, iir_lc_v = 0;    // longest chunk of each pass
     bool iir_reg_h = false, iir_reg_v = false;   // pass runs the register-resident kernel
+    bool iir_rows_h = false;               // horizontal pass writes J rows (no transposed planes)
     IirJob* d_ihj = nullptr;
     IirJob* d_ivj = nullptr;
     float2* d_itw = nullptr;

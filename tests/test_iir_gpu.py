@@ -40,6 +40,12 @@ CASES = [
     # bar measures the cancellation, not the recursion)
     (16, 4300, [1.0, math.pi / 4], [1.5, 4.0], 4, None, "mirror"),
     (2, 4200, [0.6], [2.0], 3, None, "zero"),
+    # the horizontal pass writes its lines as rows through LDS in rounds of
+    # whole waves: chunk lengths 16, 32, 40 and 48 (1024 columns: 24)
+    (30, 700, [0.9], [2.0], 4, None, "mirror"),
+    (20, 2000, [1.2, 0.5], [1.0, 3.0], 3, None, "zero"),
+    (16, 2400, [1.0], [2.5], 2, None, "mirror"),
+    (16, 2900, [0.8], [2.0], 4, None, "mirror"),
 ]
 
 
