@@ -105,6 +105,9 @@ def parse():
     ap.add_argument("--seg-rows", default="", metavar="S0,S1,..",
                     help="segment heights per frequency for every form timed (no autotuning) or, with "
                          "--isolate, for the isolated launches (default: autotuned / the plan's own)")
+    ap.add_argument("--grouping", type=int, choices=(0, 1), default=None,
+                    help="with --seg-rows: the plan's grouping option (1: the small operand sizes in one "
+                         "launch; default: the plan's own)")
     return ap.parse_args()
 
 
@@ -112,7 +115,7 @@ def precision_of(form: str) -> str:
     return "fp32" if form == "fp32_twopass" else form
 
 
-def time_form(binding, wl, img_dev, form, steps, warmup, tune=True, seg_rows=None):
+def time_form(binding, wl, img_dev, form, steps, warmup, tune=True, seg_rows=None, grouping=None):
     import torch
     H, W = img_dev.shape
     if form == "fp32_twopass":
@@ -125,7 +128,10 @@ def time_form(binding, wl, img_dev, form, steps, warmup, tune=True, seg_rows=Non
     out = torch.empty((len(wl.omegas), wl.n_orient, H, W), dtype=torch.complex64, device="cuda")
     if seg_rows:
         bank.tuning = seg_rows
+    if grouping is not None:
+        bank.grouping = grouping
     tuning = bank.autotune(img_dev, out, reps=3) if tune and not seg_rows else bank.tuning
+    grouping = bank.grouping
     for _ in range(warmup):
         bank(img_dev, out)
     torch.cuda.synchronize()
@@ -148,7 +154,7 @@ def time_form(binding, wl, img_dev, form, steps, warmup, tune=True, seg_rows=Non
     info = bank.info
     res = out.cpu().numpy()
     bank.close()
-    return ms, prof, info, res, tuning
+    return ms, prof, info, res, tuning, grouping
 
 
 def compute_peak(form: str, kernel: str) -> tuple[str, float]:
@@ -207,7 +213,7 @@ def launch_radii(name: str) -> list[int]:
     return [int(v) for v in name.rsplit("_r", 1)[1].split("_")[0].split("+")]
 
 
-def isolated_launch(binding, wl, img_dev, form, name, tuning, steps, warmup):
+def isolated_launch(binding, wl, img_dev, form, name, tuning, grouping, steps, warmup):
     """The launch `name` of the bank in a plan that holds only its frequency,
     launched alone: its event-timed average with no other launch sharing the
     chip, against the same per-launch algorithmic work."""
@@ -223,6 +229,7 @@ def isolated_launch(binding, wl, img_dev, form, name, tuning, steps, warmup):
     finally:
         os.environ.pop("LIBGABOR_ALGO", None)
     bank.tuning = [tuning[i] for i in idx]
+    bank.grouping = grouping
     out = torch.empty((len(idx), wl.n_orient, H, W), dtype=torch.complex64, device="cuda")
     for _ in range(warmup):
         bank(img_dev, out)
@@ -597,8 +604,8 @@ def main():
 
     forms, results = {}, {}
     for form in [f for f in args.forms.split(",") if f]:
-        ms, prof, info, res, tuning = time_form(binding, wl, img_dev, form, args.steps, args.warmup,
-                                                not args.no_tune, seg)
+        ms, prof, info, res, tuning, grouping = time_form(binding, wl, img_dev, form, args.steps, args.warmup,
+                                                          not args.no_tune, seg, args.grouping)
         results[form] = res
         forms[form] = {
             "value": n_out / (ms * 1e-3), "ms_per_step": round(ms, 5),
@@ -608,12 +615,14 @@ def main():
                             "real_macs": v["real_macs"], "bytes": v["bytes"]} for k, v in prof.items()},
             "real_macs_per_step": info.real_macs,
             "segment_rows": tuning,
+            "grouping": grouping,
         }
         forms[form]["roofline"]["step"] = step_roofline(form, 2 * info.real_macs, 4 * H * W + 8 * n_out,
                                                         round(ms, 5))
         if form in ("fp32", "bf16_split"):
             forms[form]["roofline"]["isolated"] = isolated_launch(
-                binding, wl, img_dev, form, forms[form]["roofline"]["kernel"], tuning, args.steps, args.warmup)
+                binding, wl, img_dev, form, forms[form]["roofline"]["kernel"], tuning, grouping, args.steps,
+                args.warmup)
         print(f"bench.py: {form} done", file=sys.stderr, flush=True)
 
     cpu = None

@@ -373,8 +373,11 @@ gabor_status lsdft_work(int32_t height, int32_t width, int32_t m_y, int32_t m_x,
  * timed launches; it then times whole applies with every height scaled by
  * 1, 2 and 4 (the frequencies run concurrently), keeps the fastest, and
  * refines it by coordinate descent on the whole apply (each frequency's
- * height retimed with the others fixed, two passes).  It synchronises
- * hip_stream.  get/set copy the chosen heights
+ * height retimed with the others fixed, two passes).  When the plan has
+ * two or more distinct small operand sizes on the wave-specialised kernel
+ * (quarters Q <= 16, i.e. radii up to 24: 16 + 2R <= 64), it repeats the whole-apply tuning with the
+ * grouping option flipped and keeps that option only if the apply gets at
+ * least 2 % faster.  It synchronises hip_stream.  get/set copy the chosen heights
  * (n = number of frequencies; 0 for frequencies on the two-pass kernels) so
  * that a caller can cache them; set rejects heights below the image height
  * that are not positive multiples of 32, and replaces every height of at
@@ -386,6 +389,21 @@ gabor_status gabor_bank_autotune(gabor_plan plan, const float* d_image, int64_t 
                                  void* d_out, int32_t reps, void* hip_stream);
 gabor_status gabor_bank_get_tuning(gabor_plan plan, int32_t* seg_rows, int32_t capacity, int32_t* n);
 gabor_status gabor_bank_set_tuning(gabor_plan plan, const int32_t* seg_rows, int32_t n);
+
+/*
+ * Grouping option (schedule only; results are bit-identical either way).
+ * An apply and a batch launch the fused frequencies once per operand size
+ * (quarter Q, contracted length 4Q), the launches running concurrently on
+ * the caller's and the plan's streams.  With group_small = 1 every tile of
+ * the small quarters (Q <= 16) goes into one launch instead, sorted by
+ * decreasing cost, whose workgroups each run their tile's quarter: fewer
+ * concurrent launches to fork and join, at the registers and LDS of the
+ * largest member.  Default 0; gabor_bank_autotune may set it.  set accepts
+ * 0 or 1 (else GABOR_ERR_INVALID_ARG) and drops the plan's cached apply
+ * graphs when the option changes; batches created afterwards follow it.
+ */
+gabor_status gabor_bank_get_grouping(gabor_plan plan, int32_t* group_small);
+gabor_status gabor_bank_set_grouping(gabor_plan plan, int32_t group_small);
 
 typedef struct gabor_plan_info {
     int32_t height, width, n_freq, n_orient;

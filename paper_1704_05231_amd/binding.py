@@ -33,7 +33,7 @@ EXPORTS = ["gabor_status_string", "gabor_bank_plan", "gabor_bank_plan_iir", "gab
            "gabor_bank_apply_adjoint_noalloc", "gabor_bank_apply_batched", "gabor_bank_apply_adjoint_batched",
            "gabor_bank_destroy", "gabor_batch_create", "gabor_batch_apply", "gabor_batch_info",
            "gabor_batch_destroy", "gabor_bank_autotune", "gabor_bank_get_tuning", "gabor_bank_set_tuning",
-           "lsdft_apply", "lsdft_work", "sdft_box_apply", "gabor_bank_plan_info", "gabor_profile_enable",
+           "gabor_bank_get_grouping", "gabor_bank_set_grouping", "lsdft_apply", "lsdft_work", "sdft_box_apply", "gabor_bank_plan_info", "gabor_profile_enable",
            "gabor_profile_read"]
 
 
@@ -107,6 +107,10 @@ def load():
     lib.gabor_bank_get_tuning.restype = ctypes.c_int
     lib.gabor_bank_set_tuning.argtypes = [P, P, i32]
     lib.gabor_bank_set_tuning.restype = ctypes.c_int
+    lib.gabor_bank_get_grouping.argtypes = [P, ctypes.POINTER(i32)]
+    lib.gabor_bank_get_grouping.restype = ctypes.c_int
+    lib.gabor_bank_set_grouping.argtypes = [P, i32]
+    lib.gabor_bank_set_grouping.restype = ctypes.c_int
     lib.lsdft_apply.argtypes = [P, i32, i32, i64, i32, i32, f64, ctypes.c_int, ctypes.c_int, P, P]
     lib.lsdft_apply.restype = ctypes.c_int
     lib.lsdft_work.argtypes = [i32, i32, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -233,6 +237,16 @@ def gabor_bank_get_tuning(plan) -> list[int]:
 def gabor_bank_set_tuning(plan, seg_rows):
     arr = np.ascontiguousarray(seg_rows, dtype=np.int32)
     _check(load().gabor_bank_set_tuning(plan, _p(arr), arr.size), "gabor_bank_set_tuning")
+
+
+def gabor_bank_get_grouping(plan) -> int:
+    g = ctypes.c_int32()
+    _check(load().gabor_bank_get_grouping(plan, ctypes.byref(g)), "gabor_bank_get_grouping")
+    return int(g.value)
+
+
+def gabor_bank_set_grouping(plan, group_small: int):
+    _check(load().gabor_bank_set_grouping(plan, int(group_small)), "gabor_bank_set_grouping")
 
 
 def gabor_batch_create(plan, d_images, heights, widths, row_strides, d_outs, stream=None):
@@ -459,6 +473,15 @@ class GaborBank:
     @tuning.setter
     def tuning(self, seg_rows):
         gabor_bank_set_tuning(self._plan, seg_rows)
+
+    @property
+    def grouping(self) -> int:
+        """1: the small operand sizes run in one launch (see gabor_bank_set_grouping)."""
+        return gabor_bank_get_grouping(self._plan)
+
+    @grouping.setter
+    def grouping(self, group_small: int):
+        gabor_bank_set_grouping(self._plan, group_small)
 
     def profile(self, enable: bool = True):
         gabor_profile_enable(self._plan, enable)

@@ -25,7 +25,7 @@
 namespace {
 
 struct BatchGroup {
-    int q;
+    int q;                     // quarter, or 0: the small quarters in one launch
     int first_tile, n_tiles;
     int64_t weight;            // total tile steps, for ordering the launches
     std::string name;          // profile name: kernel and the radii it covers
@@ -102,22 +102,33 @@ extern "C" gabor_status gabor_batch_create(gabor_batch* out, gabor_plan p, int32
     const std::vector<BatchFreq> freqs = batch_freq_table(p);
     for (int f = 0; f < p->O; ++f)
         if (!p->launches[f].fused) b->twopass_freqs.push_back(f);
-    // Tiles per quarter: image-major, then segment, strip and job (jobs of a
+    // One launch per quarter, or (plan option) one for every small quarter
+    // of the wave-specialised kernel together (key 0) when there are several.
+    auto small = [&](int q) { return p->group_small && p->use_ws && ws_small_quarter(p->fused_op, q); };
+    std::vector<int> small_qs;
+    for (int f = 0; f < p->O; ++f)
+        if (p->launches[f].fused && small(p->launches[f].q) &&
+            std::find(small_qs.begin(), small_qs.end(), p->launches[f].q) == small_qs.end())
+            small_qs.push_back(p->launches[f].q);
+    const bool merge = small_qs.size() > 1;
+    auto key_of = [&](int f) { return merge && small(p->launches[f].q) ? 0 : p->launches[f].q; };
+    // Tiles per launch: image-major, then segment, strip and job (jobs of a
     // strip share its image rows), then stably sorted by decreasing length.
     std::vector<int> qs;
     for (int f = 0; f < p->O; ++f)
-        if (p->launches[f].fused && std::find(qs.begin(), qs.end(), p->launches[f].q) == qs.end())
-            qs.push_back(p->launches[f].q);
+        if (p->launches[f].fused && std::find(qs.begin(), qs.end(), key_of(f)) == qs.end())
+            qs.push_back(key_of(f));
     std::vector<BatchTile> tiles;
-    for (int q : qs) {
+    for (int key : qs) {
         BatchGroup g{};
-        g.q = q;
+        g.q = key;
         g.first_tile = (int)tiles.size();
         std::vector<std::pair<int64_t, BatchTile>> tl;    // (cost, tile)
         for (int i = 0; i < n_images; ++i)
             for (int f = 0; f < p->O; ++f) {
                 const FreqLaunch& fl = p->launches[f];
-                if (!fl.fused || fl.q != q) continue;
+                if (!fl.fused || key_of(f) != key) continue;
+                const int q = fl.q;
                 const int h = heights[i], seg = fl.seg_rows;
                 const int n_ys = (h + seg - 1) / seg;
                 const int lead = 4 * q / 16;
@@ -149,7 +160,7 @@ extern "C" gabor_status gabor_batch_create(gabor_batch* out, gabor_plan p, int32
             const double full = (double)p->H * p->W;
             for (int f = 0; f < p->O; ++f) {
                 const FreqLaunch& fl = p->launches[f];
-                if (!fl.fused || fl.q != q) continue;
+                if (!fl.fused || key_of(f) != key) continue;
                 radii += (radii.empty() ? "" : "+") + std::to_string(p->freqs[f].R);
                 for (int i = 0; i < n_images; ++i) {
                     const double frac = (double)heights[i] * widths[i] / full;
@@ -157,7 +168,7 @@ extern "C" gabor_status gabor_batch_create(gabor_batch* out, gabor_plan p, int32
                     bytes += (double)fl.bytes * frac;
                 }
             }
-            const bool ws = p->use_ws && ws_supported(p->fused_op, q);
+            const bool ws = key == 0 || (p->use_ws && ws_supported(p->fused_op, key));
             g.name = std::string(ws ? kWsNames[p->fused_op] : kFusedNames[p->fused_op]) + "_r" + radii +
                      (n_images > 1 ? "_x" + std::to_string(n_images) : std::string());
             g.macs = (int64_t)(macs + 0.5);
@@ -217,7 +228,7 @@ extern "C" gabor_status gabor_batch_apply(gabor_batch b, void* hip_stream)
         const BatchGroup& g = b->groups[j];
         hipStream_t ls = (j == 0 || !fork) ? stream : p->aux[(j - 1) % n_aux];
         LaunchTimer tm(p, ls, g.name, g.macs, g.bytes);
-        if (p->use_ws && ws_supported(p->fused_op, g.q)) {
+        if (g.q == 0 || (p->use_ws && ws_supported(p->fused_op, g.q))) {
             // one workgroup per tile, tiles in decreasing cost
             WsTilesArgs t{};
             t.images = b->d_images;
@@ -227,7 +238,9 @@ extern "C" gabor_status gabor_batch_apply(gabor_batch b, void* hip_stream)
             t.taps = p->d_taps;
             t.n_tiles = g.n_tiles;
             t.boundary = p->boundary;
-            if (launch_ws_tiles(p->fused_op, t, g.q, ls) != hipSuccess) return GABOR_ERR_DEVICE;
+            const hipError_t e = g.q == 0 ? launch_ws_tiles_small(p->fused_op, t, ls)
+                                          : launch_ws_tiles(p->fused_op, t, g.q, ls);
+            if (e != hipSuccess) return GABOR_ERR_DEVICE;
             continue;
         }
         BatchArgs a{};

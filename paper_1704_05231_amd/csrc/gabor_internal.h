@@ -207,6 +207,12 @@ struct WsTilesArgs {
     int32_t n_tiles, boundary;
 };
 hipError_t launch_ws_tiles(int op, const WsTilesArgs& t, int Q, hipStream_t stream);
+// The small quarters (Q <= kWsSmallQuarter) in one launch: each workgroup
+// runs its tile's quarter; registers and LDS are the largest member's.
+constexpr int kWsSmallQuarter = 16;
+bool ws_small_quarter(int op, int Q);
+hipError_t launch_ws_tiles_small(int op, const WsTilesArgs& t, hipStream_t stream);
+hipError_t prepare_ws_small(int op);
 
 int stream_quarter(int op, int R);             // Q for radius R (L = 4Q >= 16 + 2R)
 size_t stream_lds_bytes(int op, int Q);
@@ -223,11 +229,13 @@ template <int OP> hipError_t batch_form(const BatchArgs& b, int Q, hipStream_t s
 template <int OP> hipError_t ws_form(const StreamArgs& a, int Q, int n_blocks, hipStream_t stream);
 template <int OP> hipError_t ws_tiles_form(const WsTilesArgs& t, int Q, hipStream_t stream);
 template <int OP> hipError_t ws_prepare_form(int Q);
+template <int OP> hipError_t ws_small_form(const WsTilesArgs* t, hipStream_t stream);   // t null: prepare only
 #define GABOR_DECLARE_FORM(OP)                                                                   \
     template <> hipError_t stream_form<OP>(const StreamArgs&, int, int, hipStream_t);            \
     template <> hipError_t ws_form<OP>(const StreamArgs&, int, int, hipStream_t);                \
     template <> hipError_t ws_tiles_form<OP>(const WsTilesArgs&, int, hipStream_t);              \
     template <> hipError_t ws_prepare_form<OP>(int);                                              \
+    template <> hipError_t ws_small_form<OP>(const WsTilesArgs*, hipStream_t);                    \
     template <> hipError_t lsdft_form<OP>(const StreamArgs&, const LsdftTaps&, int, int, hipStream_t); \
     template <> hipError_t batch_form<OP>(const BatchArgs&, int, hipStream_t);
 GABOR_DECLARE_FORM(FUSED_F32)

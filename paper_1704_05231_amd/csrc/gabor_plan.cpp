@@ -511,6 +511,10 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
             release(p);
             return GABOR_ERR_DEVICE;
         }
+    if (has_small_group(p) && prepare_ws_small(p->fused_op) != hipSuccess) {
+        release(p);
+        return GABOR_ERR_DEVICE;
+    }
     // Independent frequencies run concurrently: up to three auxiliary
     // streams beside the caller's (four hardware queues).
     const int n_conc = std::min<int>(3, (int)p->order.size() - 1);
@@ -1285,11 +1289,14 @@ extern "C" gabor_status gabor_bank_autotune(gabor_plan p, const float* d_image, 
     // The frequencies run concurrently in an apply, where fewer, longer
     // segments (less lead-in recomputation) can beat the per-launch optimum:
     // time the whole apply with every segment scaled by 1, 2 and 4.
-    if (rc == GABOR_OK && !p->fjobs.empty()) {
-        std::vector<int> base_seg(p->O), best(p->O);
-        for (int i = 0; i < p->O; ++i) base_seg[i] = best[i] = p->launches[i].seg_rows;
-        const int hmax = (p->H + 15) / 16 * 16;
+    std::vector<int> per_launch(p->O);
+    for (int i = 0; i < p->O; ++i) per_launch[i] = p->launches[i].seg_rows;
+    auto tune_whole = [&]() -> double {
         double best_t = 1e30;
+        if (rc != GABOR_OK || p->fjobs.empty()) return best_t;
+        std::vector<int> base_seg(per_launch), best(per_launch);
+        for (int i = 0; i < p->O; ++i) p->launches[i].seg_rows = per_launch[i];
+        const int hmax = (p->H + 15) / 16 * 16;
         for (int mult : {1, 2, 4}) {
             for (int i = 0; i < p->O; ++i)
                 if (p->launches[i].fused) p->launches[i].seg_rows = std::min(base_seg[i] * mult, hmax);
@@ -1323,6 +1330,23 @@ extern "C" gabor_status gabor_bank_autotune(gabor_plan p, const float* d_image, 
                 }
                 p->launches[i].seg_rows = keep;
             }
+        return best_t;
+    };
+    const double t_own = tune_whole();
+    // The small quarters grouped into one launch (the other setting of the
+    // plan's option), tuned the same way; kept only on a clear gain.
+    if (rc == GABOR_OK && has_small_group(p)) {
+        std::vector<int> own(p->O);
+        for (int i = 0; i < p->O; ++i) own[i] = p->launches[i].seg_rows;
+        const bool was = p->group_small;
+        p->group_small = !was;
+        clear_apply_graphs(p);
+        const double t_other = tune_whole();
+        if (rc == GABOR_OK && !(t_other < 0.98 * t_own)) {
+            p->group_small = was;
+            for (int i = 0; i < p->O; ++i) p->launches[i].seg_rows = own[i];
+            clear_apply_graphs(p);
+        }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
@@ -1348,6 +1372,23 @@ extern "C" gabor_status gabor_bank_set_tuning(gabor_plan p, const int32_t* seg_r
     const int hmax = (p->H + 15) / 16 * 16;
     for (int i = 0; i < n; ++i)
         if (p->launches[i].fused) p->launches[i].seg_rows = seg_rows[i] >= p->H ? hmax : seg_rows[i];
+    return GABOR_OK;
+}
+
+extern "C" gabor_status gabor_bank_get_grouping(gabor_plan p, int32_t* group_small)
+{
+    if (!p || !group_small) return GABOR_ERR_INVALID_ARG;
+    *group_small = p->group_small ? 1 : 0;
+    return GABOR_OK;
+}
+
+extern "C" gabor_status gabor_bank_set_grouping(gabor_plan p, int32_t group_small)
+{
+    if (!p || (group_small != 0 && group_small != 1)) return GABOR_ERR_INVALID_ARG;
+    if (p->group_small != (group_small == 1)) {
+        p->group_small = group_small == 1;
+        clear_apply_graphs(p);                     // cached applies hold the other launches
+    }
     return GABOR_OK;
 }
 

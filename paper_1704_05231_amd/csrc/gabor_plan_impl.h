@@ -61,6 +61,7 @@ struct gabor_plan_s {
     float2* d_iscr = nullptr;
     int fused_op = FUSED_F32;
     bool use_ws = true;                    // wave-specialised kernel where built
+    bool group_small = false;              // batch and apply: the small quarters in one launch
     int32_t n_planes = 0;
     int32_t n_row_passes = 0, n_col_passes = 0;
     int64_t row_macs = 0, col_macs = 0;
@@ -114,6 +115,19 @@ struct LaunchTimer {
 inline bool fused_on_ws(const gabor_plan_s* p, int i)
 {
     return p->launches[i].fused && p->use_ws && ws_supported(p->fused_op, p->launches[i].q);
+}
+
+// Two or more distinct small wave-specialised quarters: grouping them
+// changes the launches of an apply.
+inline bool has_small_group(const gabor_plan_s* p)
+{
+    int first = -1;
+    for (int i = 0; i < p->O; ++i)
+        if (fused_on_ws(p, i) && ws_small_quarter(p->fused_op, p->launches[i].q)) {
+            if (first < 0) first = p->launches[i].q;
+            else if (p->launches[i].q != first) return true;
+        }
+    return false;
 }
 // The plan's frequency table as the batch kernels read it (R, segment rows,
 // scales, quarter per frequency).

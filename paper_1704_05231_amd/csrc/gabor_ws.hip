@@ -433,11 +433,9 @@ __global__ __launch_bounds__(kWThreads) void k_ws(StreamArgs a)
 // cost, so the dispatcher hands out the longest tiles first and the rest as
 // workgroups free up (a dynamic queue without atomics).
 template <int OP, int Q>
-__global__ __launch_bounds__(kWThreads) void k_ws_tiles(WsTilesArgs t)
+__device__ __forceinline__ void ws_tile(const WsTilesArgs& t, const BatchTile& tl, const BatchImage& im,
+                                        const BatchFreq& fq)
 {
-    const BatchTile tl = t.tiles[blockIdx.x];
-    const BatchImage im = t.images[tl.image];
-    const BatchFreq fq = t.freqs[tl.freq];
     StreamArgs a{};
     a.img = im.img;
     a.stride = im.stride;
@@ -460,6 +458,36 @@ __global__ __launch_bounds__(kWThreads) void k_ws_tiles(WsTilesArgs t)
     else if (jb.c_real) ws_body<OP, Q, false, true>(a, jb, tl.rest);
     else ws_body<OP, Q, false, false>(a, jb, tl.rest);
 }
+
+template <int OP, int Q>
+__global__ __launch_bounds__(kWThreads) void k_ws_tiles(WsTilesArgs t)
+{
+    const BatchTile tl = t.tiles[blockIdx.x];
+    ws_tile<OP, Q>(t, tl, t.images[tl.image], t.freqs[tl.freq]);
+}
+
+// Tiles of several small quarters in one launch (sorted by decreasing cost
+// across them): each workgroup runs the body of its tile's quarter.  The
+// launch holds the largest member's registers and LDS, which for these
+// quarters leaves as many workgroups per compute unit as that member alone.
+template <int OP, int... Qs>
+__device__ __forceinline__ void ws_tile_any(const WsTilesArgs& t, const BatchTile& tl, const BatchImage& im,
+                                            const BatchFreq& fq)
+{
+    bool done = false;
+    ((!done && fq.q == Qs ? (ws_tile<OP, Qs>(t, tl, im, fq), done = true) : false), ...);
+}
+
+template <int OP>
+__global__ __launch_bounds__(kWThreads) void k_ws_tiles_small(WsTilesArgs t)
+{
+    const BatchTile tl = t.tiles[blockIdx.x];
+    const BatchImage im = t.images[tl.image];
+    const BatchFreq fq = t.freqs[tl.freq];
+    if constexpr (OP == FUSED_F32) ws_tile_any<OP, 4, 8, 12, 16>(t, tl, im, fq);
+    else ws_tile_any<OP, 8, 16>(t, tl, im, fq);
+}
+static_assert(kWsSmallQuarter == 16, "the small launch's quarter lists end at 16");
 
 // Dynamic-LDS limits of the two kernels of one form and quarter (raised at
 // plan creation, so that no launch captured in a graph needs to).
@@ -552,6 +580,18 @@ hipError_t ws_prepare_form<GABOR_FORM>(int Q)
         return prepare_ws_list<GABOR_FORM, 8, 16, 24, 32>(Q);
 }
 
+static LdsLimit ws_small_limit;
+
+template <>
+hipError_t ws_small_form<GABOR_FORM>(const WsTilesArgs* t, hipStream_t stream)
+{
+    const size_t lds = WsShape<GABOR_FORM, kWsSmallQuarter>::lds_bytes;   // the largest member's
+    const hipError_t e = ws_small_limit.ensure((const void*)k_ws_tiles_small<GABOR_FORM>, lds);
+    if (e != hipSuccess || !t) return e;
+    hipLaunchKernelGGL((k_ws_tiles_small<GABOR_FORM>), dim3(t->n_tiles), dim3(kWThreads), lds, stream, *t);
+    return hipGetLastError();
+}
+
 template <>
 hipError_t ws_tiles_form<GABOR_FORM>(const WsTilesArgs& t, int Q, hipStream_t stream)
 {
@@ -585,6 +625,37 @@ hipError_t launch_ws_tiles(int op, const WsTilesArgs& t, int Q, hipStream_t stre
         case FUSED_BF16X3: return ws_tiles_form<FUSED_BF16X3>(t, Q, stream);
         case FUSED_F16: return ws_tiles_form<FUSED_F16>(t, Q, stream);
         case FUSED_F16X3: return ws_tiles_form<FUSED_F16X3>(t, Q, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+bool ws_small_quarter(int op, int Q)
+{
+    return Q <= kWsSmallQuarter && ws_supported(op, Q);
+}
+
+hipError_t launch_ws_tiles_small(int op, const WsTilesArgs& t, hipStream_t stream)
+{
+    if (t.n_tiles <= 0) return hipSuccess;
+    if (!t.images || !t.freqs || !t.tiles || !t.jobs || !t.taps) return hipErrorInvalidValue;
+    switch (op) {
+        case FUSED_F32: return ws_small_form<FUSED_F32>(&t, stream);
+        case FUSED_BF16: return ws_small_form<FUSED_BF16>(&t, stream);
+        case FUSED_BF16X3: return ws_small_form<FUSED_BF16X3>(&t, stream);
+        case FUSED_F16: return ws_small_form<FUSED_F16>(&t, stream);
+        case FUSED_F16X3: return ws_small_form<FUSED_F16X3>(&t, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t prepare_ws_small(int op)
+{
+    switch (op) {
+        case FUSED_F32: return ws_small_form<FUSED_F32>(nullptr, nullptr);
+        case FUSED_BF16: return ws_small_form<FUSED_BF16>(nullptr, nullptr);
+        case FUSED_BF16X3: return ws_small_form<FUSED_BF16X3>(nullptr, nullptr);
+        case FUSED_F16: return ws_small_form<FUSED_F16>(nullptr, nullptr);
+        case FUSED_F16X3: return ws_small_form<FUSED_F16X3>(nullptr, nullptr);
     }
     return hipErrorInvalidValue;
 }

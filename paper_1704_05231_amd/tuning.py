@@ -52,13 +52,16 @@ def store_cache(cache: dict, path: str | None = None):
 
 
 def tuned(bank, img, out=None, reps: int = 5, path: str | None = None) -> list[int]:
-    """Apply the cached schedule of this bank, or tune and cache it."""
+    """Apply the cached schedule of this bank (segment heights and grouping
+    option), or tune and cache it; returns the segment heights."""
     cache = load_cache(path)
     k = key(bank)
-    if k in cache:
-        bank.tuning = cache[k]
-        return cache[k]
+    entry = cache.get(k)
+    if isinstance(entry, dict) and "seg_rows" in entry:
+        bank.tuning = entry["seg_rows"]
+        bank.grouping = int(entry.get("grouping", 0))
+        return entry["seg_rows"]
     seg = bank.autotune(img, out, reps)
-    cache[k] = seg
+    cache[k] = {"seg_rows": seg, "grouping": bank.grouping}
     store_cache(cache, path)
     return seg

@@ -161,6 +161,9 @@ def test_tuning_rejects_null_arguments():
     assert lib.gabor_bank_autotune(None, ctypes.c_void_p(16), 8, ctypes.c_void_p(16), 3, None) == 1
     assert lib.gabor_bank_get_tuning(None, None, 0, ctypes.byref(n)) == 1
     assert lib.gabor_bank_set_tuning(None, None, 0) == 1
+    g = ctypes.c_int32()
+    assert lib.gabor_bank_get_grouping(None, ctypes.byref(g)) == 1
+    assert lib.gabor_bank_set_grouping(None, 1) == 1
 
 
 def test_iir_plan_rejects_bad_arguments():

@@ -1,5 +1,8 @@
 """GPU checks of the schedule autotuner: tuning changes timing only, never
-results; get/set round-trip; the JSON cache reapplies a stored schedule."""
+results; get/set round-trip; the JSON cache reapplies a stored schedule; the
+grouping option (small operand sizes in one launch) keeps every bit."""
+import math
+
 import numpy as np
 import pytest
 
@@ -41,11 +44,70 @@ def test_tuning_cache_round_trip(gpu_lib, tmp_path):
     path = str(tmp_path / "tuning.json")
     bank = gpu_lib.GaborBank(200, 300, [1.0, 0.3], [2.0, 6.0], 4, None, 3.0, "zero", "fp16_split")
     seg = tuning.tuned(bank, img, reps=2, path=path)
+    grouping = bank.grouping
     bank.close()
     cache = tuning.load_cache(path)
-    assert len(cache) == 1 and list(cache.values())[0] == seg
+    assert len(cache) == 1 and list(cache.values())[0] == {"seg_rows": seg, "grouping": grouping}
     bank2 = gpu_lib.GaborBank(200, 300, [1.0, 0.3], [2.0, 6.0], 4, None, 3.0, "zero", "fp16_split")
     bank2.tuning = [32, 32]
+    bank2.grouping = 1 - grouping
     assert tuning.tuned(bank2, img, path=path) == seg      # a cache hit: no retuning
-    assert bank2.tuning == seg
+    assert bank2.tuning == seg and bank2.grouping == grouping
     bank2.close()
+
+
+# R = 6, 12, 24 (three small operand sizes in FP32, two in the 16-bit forms)
+# and 48 (its own launch)
+GROUP_OMEGAS = [math.pi / 2, math.pi / 4, math.pi / 8, math.pi / 16]
+GROUP_SIGMAS = [2.0, 4.0, 8.0, 16.0]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16_split", "fp16_split", "bf16", "fp16"])
+def test_grouping_keeps_results_bitwise(gpu_lib, prec, monkeypatch):
+    """The small quarters in one launch give the bits of one launch per
+    quarter: through the cached apply graphs (dropped when the option
+    changes), launch by launch, and in a batch of uneven images."""
+    import torch
+    H, W = 150, 210
+    host = workloads.uniform_image(H, W, 810)
+    img = torch.from_numpy(host).cuda()
+    bank = gpu_lib.GaborBank(H, W, GROUP_OMEGAS, GROUP_SIGMAS, 8, None, 3.0, "mirror", prec)
+    assert bank.grouping == 0
+    bank.tuning = [32, 64, 96, 160]
+    ref = bank(img).clone()
+    for g in (1, 0, 1):
+        bank.grouping = g
+        assert bank.grouping == g
+        for _ in range(2):                                     # first apply builds, second replays
+            got = bank(img)
+            torch.cuda.synchronize()
+            assert torch.equal(torch.view_as_real(got), torch.view_as_real(ref)), f"grouping {g}"
+    monkeypatch.setenv("LIBGABOR_NO_GRAPH", "1")
+    eager = gpu_lib.GaborBank(H, W, GROUP_OMEGAS, GROUP_SIGMAS, 8, None, 3.0, "mirror", prec)
+    eager.tuning = [32, 64, 96, 160]
+    eager.grouping = 1
+    got = eager(img)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.view_as_real(got), torch.view_as_real(ref))
+    eager.close()
+    monkeypatch.delenv("LIBGABOR_NO_GRAPH")
+    with pytest.raises(gpu_lib.GaborError):
+        bank.grouping = 2
+    # a batch of uneven images under either option
+    sizes = [(150, 210), (37, 53), (1, 90), (64, 1), (100, 130)]
+    views = [torch.from_numpy(workloads.uniform_image(h, w, 820 + i)).cuda() for i, (h, w) in enumerate(sizes)]
+    views[0] = img
+    outs = {}
+    for g in (0, 1):
+        bank.grouping = g
+        batch = gpu_lib.GaborBatch(bank, views)
+        n_launch, _ = batch.info
+        outs[g] = [o.clone() for o in batch()]
+        torch.cuda.synchronize()
+        # FP32: R = 6, 12, 24 share a launch; 16-bit forms: R = 12 and 24 already share a quarter
+        assert n_launch == (4 if prec == "fp32" else 3) - (0 if g == 0 else (2 if prec == "fp32" else 1))
+        batch.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(torch.view_as_real(a), torch.view_as_real(b))
+    assert torch.equal(torch.view_as_real(outs[0][0]), torch.view_as_real(ref))
+    bank.close()
