@@ -15,7 +15,9 @@
 // FP32 two-pass kernels on the caller's stream, one launch per pass over all
 // images, each image with J planes of its own in a batch-owned workspace.
 #include <algorithm>
+#include <array>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -31,6 +33,45 @@ struct BatchGroup {
     std::string name;          // profile name: kernel and the radii it covers
     int64_t macs, bytes;       // algorithmic work of one launch
 };
+
+// Dispatch order of a launch's tiles: decreasing cost (the dispatcher hands
+// out the longest tiles first and the rest as workgroups free up), and
+// within each run of equal cost, the tiles of eight strip segments (same
+// image, frequency, strip and rows: the same image rows) interleaved: the
+// first tile of each of the eight, then the second of each, ...  Workgroup b
+// of a launch goes to XCD b mod 8, each XCD with its own L2, so a strip
+// segment's equal-cost jobs (the pairs of a frequency) then run on one XCD
+// one after another instead of on three.
+constexpr int kXcds = 8;
+void xcd_order(std::vector<std::pair<int64_t, BatchTile>>& tl)
+{
+    std::stable_sort(tl.begin(), tl.end(), [](const auto& a, const auto& c) { return a.first > c.first; });
+    std::vector<std::pair<int64_t, BatchTile>> out;
+    out.reserve(tl.size());
+    for (size_t r0 = 0; r0 < tl.size();) {
+        size_t r1 = r0;
+        while (r1 < tl.size() && tl[r1].first == tl[r0].first) ++r1;
+        // strip segments of the run, in order of first appearance
+        std::vector<std::vector<size_t>> segs;
+        std::map<std::array<int32_t, 3>, size_t> index;
+        for (size_t k = r0; k < r1; ++k) {
+            const BatchTile& t = tl[k].second;
+            const auto it = index.emplace(std::array<int32_t, 3>{t.image, t.freq, t.rest}, segs.size()).first;
+            if (it->second == segs.size()) segs.emplace_back();
+            segs[it->second].push_back(k);
+        }
+        for (size_t s0 = 0; s0 < segs.size(); s0 += kXcds) {
+            const size_t s1 = std::min(segs.size(), s0 + kXcds);
+            size_t most = 0;
+            for (size_t k = s0; k < s1; ++k) most = std::max(most, segs[k].size());
+            for (size_t j = 0; j < most; ++j)
+                for (size_t k = s0; k < s1; ++k)
+                    if (j < segs[k].size()) out.push_back(tl[segs[k][j]]);
+        }
+        r0 = r1;
+    }
+    tl.swap(out);
+}
 
 }  // namespace
 
@@ -174,7 +215,7 @@ extern "C" gabor_status gabor_batch_create(gabor_batch* out, gabor_plan p, int32
             g.macs = (int64_t)(macs + 0.5);
             g.bytes = (int64_t)(bytes + 0.5);
         }
-        std::stable_sort(tl.begin(), tl.end(), [](const auto& a, const auto& c) { return a.first > c.first; });
+        xcd_order(tl);
         if ((int64_t)tiles.size() + (int64_t)tl.size() > 0x7fffffffLL) {
             batch_release(b);
             return GABOR_ERR_UNSUPPORTED;
