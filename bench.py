@@ -130,7 +130,7 @@ def time_form(binding, wl, img_dev, form, steps, warmup, tune=True, seg_rows=Non
         bank.tuning = seg_rows
     if grouping is not None:
         bank.grouping = grouping
-    tuning = bank.autotune(img_dev, out, reps=3) if tune and not seg_rows else bank.tuning
+    tuning = bank.autotune(img_dev, out, reps=5) if tune and not seg_rows else bank.tuning
     grouping = bank.grouping
     for _ in range(warmup):
         bank(img_dev, out)
@@ -338,8 +338,13 @@ def bench_lsdft(binding, workloads, steps, warmup):
         t = traffic.get(form)
         if t:
             roof.update({"traffic": t["hbm_bytes"], "traffic_detail": t})
+        per_bin = np.abs(got - ref).max(0) / peak                 # [M_y, M_x], relative to each bin's peak
+        worst = np.unravel_index(int(np.argmax(per_bin)), per_bin.shape)
         res["forms"][form] = {"ms": round(ms, 5), "value": wl.my * wl.mx * H * W / (ms * 1e-3),
-                              "max_rel_err_per_bin": float((np.abs(got - ref).max(0) / peak).max()),
+                              "max_rel_err_per_bin": float(per_bin.max()),
+                              "median_rel_err_per_bin": float(np.median(per_bin)),
+                              "worst_bin_vu": [int(worst[0]), int(worst[1])],
+                              "rel_err_per_bin": [[float("%.2g" % e) for e in row] for row in per_bin],
                               "roofline": roof}
     res["unit"] = UNIT
     res["algorithmic_bytes"] = nbytes
