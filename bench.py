@@ -382,6 +382,7 @@ def bench_batch(binding, workloads, steps, warmup):
     frequencies pi/2 .. pi/32 (R up to 96), mirror: one gabor_batch_apply."""
     import oracle
     import torch
+    from paper_1704_05231_amd import tuning
     wl = workloads.bank_batch()
     H = max(im.shape[0] for im in wl.images)
     W = max(im.shape[1] for im in wl.images)
@@ -391,17 +392,9 @@ def bench_batch(binding, workloads, steps, warmup):
     res = {"workload": wl.name, "images": len(imgs), "outputs_per_call": n_out, "unit": UNIT, "forms": {}}
     for form in ["fp32", "bf16_split"]:
         bank = binding.GaborBank(H, W, wl.omegas, wl.sigmas, wl.n_orient, None, 3.0, wl.boundary, form)
-        # the grouping option is a schedule choice (bit-identical results): time
-        # the batch under both settings and keep the faster
-        by_grouping = {}
-        for g in (0, 1):
-            bank.grouping = g
-            trial = binding.GaborBatch(bank, imgs)
-            by_grouping[g] = event_time(trial, steps, warmup)
-            trial.close()
-            del trial
-        grouping = min(by_grouping, key=by_grouping.get)
-        bank.grouping = grouping
+        # schedule (segment heights, grouping option) tuned on whole batches;
+        # results do not depend on it
+        sched = tuning.tune_batch(bank, imgs)
         batch = binding.GaborBatch(bank, imgs)
         ms = event_time(batch, steps, warmup)
         n_launch, n_tiles = batch.info
@@ -427,8 +420,7 @@ def bench_batch(binding, workloads, steps, warmup):
             worst = max(worst, float((np.abs(got - ref).max(0) / np.abs(ref).max(0)).max()))
         res["forms"][form] = {"ms": round(ms, 4), "value": n_out / (ms * 1e-3),
                               "ms_graph_replay": round(ms_graph, 4), "value_graph_replay": n_out / (ms_graph * 1e-3),
-                              "persistent_launches": n_launch, "tiles": n_tiles, "grouping": grouping,
-                              "ms_by_grouping": {str(g): round(t, 4) for g, t in by_grouping.items()},
+                              "persistent_launches": n_launch, "tiles": n_tiles, "schedule": sched,
                               "max_rel_err_sampled": worst,
                               "roofline": hbm_roofline(nbytes, ms_graph, "whole batch per graph replay "
                                                                          "(one launch per operand size)")}

@@ -65,3 +65,44 @@ def tuned(bank, img, out=None, reps: int = 5, path: str | None = None) -> list[i
     cache[k] = {"seg_rows": seg, "grouping": bank.grouping}
     store_cache(cache, path)
     return seg
+
+
+def tune_batch(bank, images, reps: int = 3, mults=(1, 2, 4)) -> dict:
+    """Schedule of a batch of uneven images (segment heights and grouping
+    option) by timing whole batches: the bank's current heights scaled by
+    each of `mults` (capped at the plan height), under both grouping
+    settings; the fastest is applied to the bank.  With many images there is
+    parallelism enough for longer segments (less lead-in) than a single
+    image's tuning picks.  Results do not depend on the choice.  Returns the
+    chosen schedule and every candidate's time (ms, median of `reps` timed
+    batches after one warm-up)."""
+    import torch
+    base = bank.tuning
+    hmax = (bank.height + 15) // 16 * 16
+    times = {}
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def scaled(m):
+        # frequencies on the two-pass kernels report 0 and take any height
+        return [min(s * m, hmax) if s else hmax for s in base]
+
+    for g in (0, 1):
+        for m in mults:
+            bank.tuning = scaled(m)
+            bank.grouping = g
+            batch = binding.GaborBatch(bank, images)
+            batch()
+            ts = []
+            for _ in range(reps):
+                start.record()
+                batch()
+                stop.record()
+                stop.synchronize()
+                ts.append(start.elapsed_time(stop))
+            batch.close()
+            times[(g, m)] = sorted(ts)[len(ts) // 2]
+    g, m = min(times, key=times.get)
+    bank.tuning = scaled(m)
+    bank.grouping = g
+    return {"seg_rows": bank.tuning, "grouping": g,
+            "candidates_ms": {f"grouping {gg}, x{mm}": round(t, 4) for (gg, mm), t in times.items()}}

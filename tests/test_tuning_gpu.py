@@ -111,3 +111,29 @@ def test_grouping_keeps_results_bitwise(gpu_lib, prec, monkeypatch):
         assert torch.equal(torch.view_as_real(a), torch.view_as_real(b))
     assert torch.equal(torch.view_as_real(outs[0][0]), torch.view_as_real(ref))
     bank.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16_split"])
+def test_batch_tuner_keeps_results_bitwise(gpu_lib, prec):
+    """tuning.tune_batch picks segment heights and the grouping option by
+    timing whole batches; the batch's outputs keep every bit."""
+    import torch
+    from paper_1704_05231_amd import tuning
+    sizes = [(150, 210), (37, 53), (1, 90), (64, 1), (100, 130), (150, 150)]
+    views = [torch.from_numpy(workloads.uniform_image(h, w, 830 + i)).cuda() for i, (h, w) in enumerate(sizes)]
+    bank = gpu_lib.GaborBank(150, 210, GROUP_OMEGAS, GROUP_SIGMAS, 8, None, 3.0, "mirror", prec)
+    batch = gpu_lib.GaborBatch(bank, views)
+    ref = [o.clone() for o in batch()]
+    torch.cuda.synchronize()
+    batch.close()
+    sched = tuning.tune_batch(bank, views, reps=2)
+    print(f"{prec}: batch schedule {sched}")
+    assert sched["seg_rows"] == bank.tuning and sched["grouping"] == bank.grouping
+    assert len(sched["candidates_ms"]) == 6
+    batch = gpu_lib.GaborBatch(bank, views)
+    got = batch()
+    torch.cuda.synchronize()
+    for a, b in zip(ref, got):
+        assert torch.equal(torch.view_as_real(a), torch.view_as_real(b))
+    batch.close()
+    bank.close()
