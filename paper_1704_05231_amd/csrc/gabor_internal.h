@@ -186,10 +186,14 @@ struct LsdftTaps {
 
 // Wave-specialised streaming kernel (gabor_ws.hip): the same jobs and
 // results as launch_stream, eight waves per workgroup (four on the
-// horizontal pass, four on the vertical one), quarters up to kWsMaxQuarter,
-// segments of any multiple of 16 rows.
-constexpr int kWsMaxQuarter = 32;
+// horizontal pass, four on the vertical one), quarters up to
+// ws_max_quarter(op) (FP32 52, single 16-bit 56, split 40), segments of any
+// multiple of 16 rows.
+int ws_max_quarter(int op);
 bool ws_supported(int op, int Q);
+// Q for radius R on the wave-specialised kernel: L = 4Q >= 16 + 2R, a
+// multiple of 16 (FP32) or 32 (16-bit forms) whatever R.
+int ws_quarter(int op, int R);
 hipError_t launch_ws(int op, const StreamArgs& a, int Q, hipStream_t stream);
 // Raises the dynamic-LDS limits of the wave-specialised kernels of (op, Q)
 // once, outside any graph capture (plan creation).

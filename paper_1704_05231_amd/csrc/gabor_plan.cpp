@@ -357,7 +357,11 @@ extern "C" gabor_status gabor_bank_plan(gabor_plan* out, int32_t height, int32_t
             f_col_macs += (int64_t)((jb.c_real ? 1 : 2) * (jb.j_real ? 1 : 2)) * fd.K * npix;
             f_outs += (jb.out_b >= 0 ? 2 : 1) * npix;
         }
-        const int q = stream_quarter(p->fused_op, fd.R);
+        // the wave-specialised kernel's quarter where it covers R (for FP32
+        // beyond R = 56 a contraction 16 rather than 32 rows longer than the
+        // band), else the four-wave kernel's
+        int q = stream_quarter(p->fused_op, fd.R);
+        if (p->use_ws && ws_supported(p->fused_op, ws_quarter(p->fused_op, fd.R))) q = ws_quarter(p->fused_op, fd.R);
         const bool fused = q <= kStreamMaxQuarter && algo != ALGO_TWOPASS && npix <= (int64_t(1) << 27);
         // Frequencies outside the fused kernel's range run the FP32 two-pass
         // kernels whatever the requested precision (never less accurate).

@@ -566,18 +566,24 @@ template <>
 hipError_t ws_form<GABOR_FORM>(const StreamArgs& a, int Q, int n_blocks, hipStream_t stream)
 {
     if constexpr (GABOR_FORM == FUSED_F32)
-        return launch_ws_list<GABOR_FORM, 4, 8, 12, 16, 20, 24, 28, 32>(a, Q, n_blocks, stream);
+        return launch_ws_list<GABOR_FORM, 4, 8, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48, 52>(a, Q, n_blocks, stream);
     else
-        return launch_ws_list<GABOR_FORM, 8, 16, 24, 32>(a, Q, n_blocks, stream);
+        if constexpr (Form<GABOR_FORM>::split)
+            return launch_ws_list<GABOR_FORM, 8, 16, 24, 32, 40>(a, Q, n_blocks, stream);
+        else
+            return launch_ws_list<GABOR_FORM, 8, 16, 24, 32, 40, 48, 56>(a, Q, n_blocks, stream);
 }
 
 template <>
 hipError_t ws_prepare_form<GABOR_FORM>(int Q)
 {
     if constexpr (GABOR_FORM == FUSED_F32)
-        return prepare_ws_list<GABOR_FORM, 4, 8, 12, 16, 20, 24, 28, 32>(Q);
+        return prepare_ws_list<GABOR_FORM, 4, 8, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48, 52>(Q);
     else
-        return prepare_ws_list<GABOR_FORM, 8, 16, 24, 32>(Q);
+        if constexpr (Form<GABOR_FORM>::split)
+            return prepare_ws_list<GABOR_FORM, 8, 16, 24, 32, 40>(Q);
+        else
+            return prepare_ws_list<GABOR_FORM, 8, 16, 24, 32, 40, 48, 56>(Q);
 }
 
 static LdsLimit ws_small_limit;
@@ -596,9 +602,12 @@ template <>
 hipError_t ws_tiles_form<GABOR_FORM>(const WsTilesArgs& t, int Q, hipStream_t stream)
 {
     if constexpr (GABOR_FORM == FUSED_F32)
-        return launch_ws_tiles_list<GABOR_FORM, 4, 8, 12, 16, 20, 24, 28, 32>(t, Q, stream);
+        return launch_ws_tiles_list<GABOR_FORM, 4, 8, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48, 52>(t, Q, stream);
     else
-        return launch_ws_tiles_list<GABOR_FORM, 8, 16, 24, 32>(t, Q, stream);
+        if constexpr (Form<GABOR_FORM>::split)
+            return launch_ws_tiles_list<GABOR_FORM, 8, 16, 24, 32, 40>(t, Q, stream);
+        else
+            return launch_ws_tiles_list<GABOR_FORM, 8, 16, 24, 32, 40, 48, 56>(t, Q, stream);
 }
 
 #if GABOR_FORM == 0
@@ -673,9 +682,24 @@ hipError_t prepare_ws(int op, int Q)
     return hipErrorInvalidValue;
 }
 
+int ws_quarter(int op, int R)
+{
+    const int need = 16 + 2 * R;
+    return op == FUSED_F32 ? (need + 15) / 16 * 4 : (need + 31) / 32 * 8;
+}
+
+int ws_max_quarter(int op)
+{
+    // Registers without spills (each wave holds one pass's band fragments:
+    // FP32 Q = 52 128 + 110 per lane, single 16-bit Q = 56 229, split Q = 40
+    // 251; one more step spills) and LDS within 160 KB (FP32 Q = 52 147 KB)
+    if (op == FUSED_F32) return 52;
+    return op == FUSED_BF16X3 || op == FUSED_F16X3 ? 40 : 56;
+}
+
 bool ws_supported(int op, int Q)
 {
-    if (Q > kWsMaxQuarter) return false;
+    if (Q > ws_max_quarter(op)) return false;
     return op == FUSED_F32 ? Q % 4 == 0 : Q % 8 == 0;
 }
 
