@@ -370,8 +370,9 @@ gabor_status lsdft_work(int32_t height, int32_t width, int32_t m_y, int32_t m_x,
  * recomputes a lead-in of about 2R rows of the horizontal pass).  gabor_bank_autotune times every candidate
  * segment height per fused frequency on the caller's image and output
  * buffers (d_out is overwritten) and keeps the fastest median of `reps`
- * timed launches; it then times whole applies with every height scaled by
- * 1, 2 and 4 (the frequencies run concurrently), keeps the fastest, and
+ * timed launches; it then times whole applies (median over `reps` bursts of
+ * 8 back-to-back applies) with every height scaled by 1, 2 and 4 (the
+ * frequencies run concurrently), keeps the fastest, and
  * refines it by coordinate descent on the whole apply (each frequency's
  * height retimed with the others fixed, two passes).  When the plan has
  * two or more distinct small operand sizes on the wave-specialised kernel

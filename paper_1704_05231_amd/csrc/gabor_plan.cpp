@@ -1228,21 +1228,33 @@ static std::vector<int> seg_candidates(int H, int q, bool ws)
 
 // Median of reps timed applies (after one untimed one), in ms; sets *rc on
 // a device error.
+// Whole-apply time of the current schedule: one apply that builds its batch
+// and graph, then the median over `reps` bursts of kTuneBurst back-to-back
+// applies (the rate of repeated applies, with the launch latency of one
+// overlapping the work of the one before, as a caller applying the bank in a
+// loop sees it).
+constexpr int kTuneBurst = 8;
 static double time_apply(gabor_plan p, const float* d_image, int64_t row_stride_elems, void* d_out, void* hip_stream,
                          int reps, hipEvent_t a, hipEvent_t b, gabor_status* rc)
 {
     hipStream_t stream = (hipStream_t)hip_stream;
+    if (gabor_bank_apply(p, d_image, row_stride_elems, d_out, hip_stream) != GABOR_OK ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+        *rc = GABOR_ERR_DEVICE;
+        return 1e30;
+    }
     std::vector<float> t;
-    for (int r = 0; r <= reps; ++r) {
+    for (int r = 0; r < reps; ++r) {
         float ms = 0.0f;
-        if (hipEventRecord(a, stream) != hipSuccess ||
-            gabor_bank_apply(p, d_image, row_stride_elems, d_out, hip_stream) != GABOR_OK ||
-            hipEventRecord(b, stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        bool ok = hipEventRecord(a, stream) == hipSuccess;
+        for (int k = 0; ok && k < kTuneBurst; ++k)
+            ok = gabor_bank_apply(p, d_image, row_stride_elems, d_out, hip_stream) == GABOR_OK;
+        if (!ok || hipEventRecord(b, stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
             hipEventElapsedTime(&ms, a, b) != hipSuccess) {
             *rc = GABOR_ERR_DEVICE;
             return 1e30;
         }
-        if (r > 0) t.push_back(ms);
+        t.push_back(ms / kTuneBurst);
     }
     std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
     return t[t.size() / 2];
