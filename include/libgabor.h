@@ -378,7 +378,7 @@ gabor_status lsdft_work(int32_t height, int32_t width, int32_t m_y, int32_t m_x,
  * two or more distinct small operand sizes on the wave-specialised kernel
  * (quarters Q <= 16, i.e. radii up to 24: 16 + 2R <= 64), it repeats the whole-apply tuning with the
  * grouping option flipped and keeps that option only if the apply gets at
- * least 2 % faster.  It synchronises hip_stream.  get/set copy the chosen heights
+ * least 1 % faster.  It synchronises hip_stream.  get/set copy the chosen heights
  * (n = number of frequencies; 0 for frequencies on the two-pass kernels) so
  * that a caller can cache them; set rejects heights below the image height
  * that are not positive multiples of 32, and replaces every height of at

@@ -1319,7 +1319,7 @@ extern "C" gabor_status gabor_bank_autotune(gabor_plan p, const float* d_image, 
             const double t_med = time_apply(p, d_image, row_stride_elems, d_out, hip_stream, reps, a, b, &rc);
             if (rc != GABOR_OK) break;
             // a scaled schedule must beat the per-launch optimum clearly
-            const double tm = t_med * (mult == 1 ? 1.0 : 1.03);
+            const double tm = t_med * (mult == 1 ? 1.0 : 1.01);
             if (tm < best_t) {
                 best_t = tm;
                 for (int i = 0; i < p->O; ++i) best[i] = p->launches[i].seg_rows;
@@ -1339,7 +1339,7 @@ extern "C" gabor_status gabor_bank_autotune(gabor_plan p, const float* d_image, 
                     p->launches[i].seg_rows = seg;
                     const double tm = time_apply(p, d_image, row_stride_elems, d_out, hip_stream, reps, a, b, &rc);
                     if (rc != GABOR_OK) break;
-                    if (tm < 0.98 * best_t) {            // a clear gain only
+                    if (tm < 0.99 * best_t) {            // a clear gain only
                         best_t = tm;
                         keep = seg;
                     }
@@ -1358,7 +1358,7 @@ extern "C" gabor_status gabor_bank_autotune(gabor_plan p, const float* d_image, 
         p->group_small = !was;
         clear_apply_graphs(p);
         const double t_other = tune_whole();
-        if (rc == GABOR_OK && !(t_other < 0.98 * t_own)) {
+        if (rc == GABOR_OK && !(t_other < 0.99 * t_own)) {
             p->group_small = was;
             for (int i = 0; i < p->O; ++i) p->launches[i].seg_rows = own[i];
             clear_apply_graphs(p);
