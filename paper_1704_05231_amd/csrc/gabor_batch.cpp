@@ -5,13 +5,15 @@
 //
 // Frequencies on the fused kernels are grouped by operand quarter Q; each
 // group is one launch over the tiles (image, job, strip segment) of every
-// image, sorted by decreasing cost.  On the wave-specialised kernel tile b
-// is workgroup b, so the dispatcher hands out the longest tiles first and
-// the rest as workgroups free up; quarters beyond it run the persistent
+// image, in decreasing cost.  On the wave-specialised kernel tile b is
+// workgroup b, so the dispatcher hands out the longest tiles first and the
+// rest as workgroups free up; quarters beyond it run the persistent
 // four-wave kernel, each workgroup striding over the table.  One kernel
 // over all quarters would carry the largest quarter's registers and LDS
 // into every tile (measured: 185 to 256 registers with spills against 124
-// to 177 per quarter), so each quarter keeps a launch of its own.  Frequencies outside the fused kernel's range run the
+// to 177 per quarter), so each quarter keeps a launch of its own, except
+// that the plan's grouping option puts the small quarters (whose resources
+// are close) into one.  Frequencies outside the fused kernel's range run the
 // FP32 two-pass kernels on the caller's stream, one launch per pass over all
 // images, each image with J planes of its own in a batch-owned workspace.
 #include <algorithm>
@@ -154,7 +156,7 @@ extern "C" gabor_status gabor_batch_create(gabor_batch* out, gabor_plan p, int32
     const bool merge = small_qs.size() > 1;
     auto key_of = [&](int f) { return merge && small(p->launches[f].q) ? 0 : p->launches[f].q; };
     // Tiles per launch: image-major, then segment, strip and job (jobs of a
-    // strip share its image rows), then stably sorted by decreasing length.
+    // strip share its image rows), then put in dispatch order (xcd_order).
     std::vector<int> qs;
     for (int f = 0; f < p->O; ++f)
         if (p->launches[f].fused && std::find(qs.begin(), qs.end(), key_of(f)) == qs.end())
