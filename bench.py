@@ -59,8 +59,8 @@ SDFT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sdft-box-512sq-16x16
 SDFT_SOURCES = ["paper_1704_05231_amd/csrc/gabor_sdft.hip"]
 # the same for the localized SDFT launch (k_lsdft) and the recursive smoother
 LSDFT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lsdft-512sq-16x16.json")
-LSDFT_SOURCES = ["paper_1704_05231_amd/csrc/gabor_fused.hip", "paper_1704_05231_amd/csrc/gabor_mfma.h",
-                 "paper_1704_05231_amd/csrc/gabor_lsdft.cpp"]
+LSDFT_SOURCES = ["paper_1704_05231_amd/csrc/gabor_ws.hip", "paper_1704_05231_amd/csrc/gabor_fused.hip",
+                 "paper_1704_05231_amd/csrc/gabor_mfma.h", "paper_1704_05231_amd/csrc/gabor_lsdft.cpp"]
 IIR_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_iir-bank-1024sq-8x4-mirror.json")
 IIR_SOURCES = ["paper_1704_05231_amd/csrc/gabor_iir.hip"]
 

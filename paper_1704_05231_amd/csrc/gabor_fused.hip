@@ -1112,6 +1112,9 @@ hipError_t launch_lsdft(int op, const StreamArgs& a, const LsdftTaps& t, int Q, 
     if (t.m[0] < 1 || t.m[0] > kLsdftMaxM || t.m[1] < 1 || t.m[1] > kLsdftMaxM) return hipErrorInvalidValue;
     if (a.n_jobs != (t.m[0] / 2 + 1) * (t.m[1] / 2 + 1) || 2 * a.R < t.m[0] - 1 || 2 * a.R < t.m[1] - 1)
         return hipErrorInvalidValue;
+    // the wave-specialised kernel where it covers the quarter (every window
+    // up to M = 64), else the four-wave one
+    if (ws_supported(op, Q)) return launch_ws_lsdft(op, a, t, Q, stream);
     if (!stream_args_ok(a, Q))
         return hipErrorInvalidValue;
     const long long nb = (long long)a.n_xs * a.n_ys * a.n_jobs;

@@ -195,6 +195,9 @@ bool ws_supported(int op, int Q);
 // multiple of 16 (FP32) or 32 (16-bit forms) whatever R.
 int ws_quarter(int op, int R);
 hipError_t launch_ws(int op, const StreamArgs& a, int Q, hipStream_t stream);
+// The localized SDFT on the wave-specialised kernel (the same jobs and
+// results as launch_lsdft's four-wave kernel).
+hipError_t launch_ws_lsdft(int op, const StreamArgs& a, const LsdftTaps& t, int Q, hipStream_t stream);
 // Raises the dynamic-LDS limits of the wave-specialised kernels of (op, Q)
 // once, outside any graph capture (plan creation).
 hipError_t prepare_ws(int op, int Q);
@@ -233,12 +236,15 @@ template <int OP> hipError_t batch_form(const BatchArgs& b, int Q, hipStream_t s
 template <int OP> hipError_t ws_form(const StreamArgs& a, int Q, int n_blocks, hipStream_t stream);
 template <int OP> hipError_t ws_tiles_form(const WsTilesArgs& t, int Q, hipStream_t stream);
 template <int OP> hipError_t ws_prepare_form(int Q);
+template <int OP> hipError_t ws_lsdft_form(const StreamArgs& a, const LsdftTaps& t, int Q, int n_blocks,
+                                           hipStream_t stream);
 template <int OP> hipError_t ws_small_form(const WsTilesArgs* t, hipStream_t stream);   // t null: prepare only
 #define GABOR_DECLARE_FORM(OP)                                                                   \
     template <> hipError_t stream_form<OP>(const StreamArgs&, int, int, hipStream_t);            \
     template <> hipError_t ws_form<OP>(const StreamArgs&, int, int, hipStream_t);                \
     template <> hipError_t ws_tiles_form<OP>(const WsTilesArgs&, int, hipStream_t);              \
     template <> hipError_t ws_prepare_form<OP>(int);                                              \
+    template <> hipError_t ws_lsdft_form<OP>(const StreamArgs&, const LsdftTaps&, int, int, hipStream_t); \
     template <> hipError_t ws_small_form<OP>(const WsTilesArgs*, hipStream_t);                    \
     template <> hipError_t lsdft_form<OP>(const StreamArgs&, const LsdftTaps&, int, int, hipStream_t); \
     template <> hipError_t batch_form<OP>(const BatchArgs&, int, hipStream_t);

@@ -58,9 +58,13 @@ struct WsShape {
 
 // JR: J is real (horizontal taps have no sine part); CR: vertical taps have
 // no sine part (compile-time, so no branch separates a matrix-core chain
-// from the reads of its result).
-template <int OP, int Q, bool JR, bool CR>
-__device__ __forceinline__ void ws_body(const StreamArgs& a, const FusedJob& jb, int job_rest)
+// from the reads of its result).  LS: a localized SDFT job (Sec. III): the
+// taps are formed from the window weights and twiddles in lt for bins
+// (u, v), and the job also stores conj(F_a) and conj(F_b) to the planes
+// out_c, out_d (Eq. (20)).
+template <int OP, int Q, bool JR, bool CR, bool LS = false>
+__device__ __forceinline__ void ws_body(const StreamArgs& a, const FusedJob& jb, int job_rest,
+                                        const LsdftTaps* lt = nullptr, int u = 0, int v = 0)
 {
     using F = Form<OP>;
     using S = WsShape<OP, Q>;
@@ -91,7 +95,29 @@ __device__ __forceinline__ void ws_body(const StreamArgs& a, const FusedJob& jb,
     const int tid = threadIdx.x;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int w = wid & 3, lane = tid & 63, o = lane & 15, g = lane >> 4;
-    const float* tab = a.taps + jb.tap_off;                 // [4][L + 16]: row c, row d, col c, col d
+    // [4][L + 16]: row c, row d, col c, col d.  A localized SDFT job forms
+    // them first: krev[T] = w[j] exp(-i 2 pi b j / M) at window offset
+    // j = T - (R - M/2) (Eq. (17)-(18)), b = u along x and v along y, the FP64
+    // product of the window weight and the exact twiddle of index b j mod M
+    // rounded once; the table sits in the J ring, which no pass uses before
+    // every wave has read its bands.
+    const float* tab = a.taps + jb.tap_off;
+    if constexpr (LS) {
+        float* tl = reinterpret_cast<float*>(ws_lds4) + 16;      // past the prologue sums
+        for (int i = tid; i < 4 * KT; i += kWThreads) {
+            const int set = i / KT, axis = set >> 1;
+            const int M = lt->m[axis], j = i - set * KT - 16 - (R - M / 2);
+            float val = 0.0f;
+            if (j >= 0 && j < M) {
+                const int idx = ((axis ? v : u) * j) % M;
+                const double wgt = lt->win[axis][j];
+                val = (set & 1) ? (float)(-wgt * lt->tw[axis][1][idx]) : (float)(wgt * lt->tw[axis][0][idx]);
+            }
+            tl[i] = val;
+        }
+        lds_barrier();                                             // B0 (this job kind only)
+        tab = tl;
+    }
     const float in_s = F::scaled ? a.in_scale : 1.0f, mid_s = F::scaled ? a.mid_scale : 1.0f;
     const float out_s = F::scaled ? a.out_scale : 1.0f;
     auto sc = [](float x, float k) { return F::scaled ? x * k : x; };
@@ -311,6 +337,10 @@ __device__ __forceinline__ void ws_body(const StreamArgs& a, const FusedJob& jb,
         const __amdgpu_buffer_rsrc_t out_b = jb.out_b >= 0
             ? make_rsrc(a.out + (int64_t)jb.out_b * plane, plane_bytes)
             : make_rsrc(a.out, 0u);                              // no partner: every store dropped
+        const __amdgpu_buffer_rsrc_t out_c = LS && jb.out_c >= 0
+            ? make_rsrc(a.out + (int64_t)jb.out_c * plane, plane_bytes) : make_rsrc(a.out, 0u);
+        const __amdgpu_buffer_rsrc_t out_d = LS && jb.out_d >= 0
+            ? make_rsrc(a.out + (int64_t)jb.out_d * plane, plane_bytes) : make_rsrc(a.out, 0u);
         // Output offsets: a per-lane base plus a wave-uniform row term.  The
         // last block of a segment that reaches the image bottom may pass it
         // (at most 15 rows: no 32-bit wrap for planes of at most 2^30 bytes);
@@ -387,6 +417,13 @@ __device__ __forceinline__ void ws_body(const StreamArgs& a, const FusedJob& jb,
                 }
                 __builtin_amdgcn_raw_buffer_store_b64(va, out_a, (int)off, 0, kStoreNT);
                 if constexpr (!JR) __builtin_amdgcn_raw_buffer_store_b64(vb, out_b, (int)off, 0, kStoreNT);
+                if constexpr (LS) {
+                    // the conjugate bins; absent planes have empty resources
+                    va[1] ^= (int)0x80000000;
+                    vb[1] ^= (int)0x80000000;
+                    __builtin_amdgcn_raw_buffer_store_b64(va, out_c, (int)off, 0, kStoreNT);
+                    if constexpr (!JR) __builtin_amdgcn_raw_buffer_store_b64(vb, out_d, (int)off, 0, kStoreNT);
+                }
             }
         };
         lds_barrier();                                             // B1
@@ -489,6 +526,33 @@ __global__ __launch_bounds__(kWThreads) void k_ws_tiles_small(WsTilesArgs t)
 }
 static_assert(kWsSmallQuarter == 16, "the small launch's quarter lists end at 16");
 
+// Localized SDFT (Sec. III) on the wave-specialised structure: job (u, v),
+// u <= Mx/2, v <= My/2, computes J_u once (Eq. (18)), F_{u,v} and
+// F_{Mx-u,v} from J_u and its conjugate (Eq. (19)), and stores the
+// conjugates to F_{Mx-u,My-v} and F_{u,My-v} (Eq. (20)); planes are indexed
+// v Mx + u.  Bins u in {0, Mx/2} have a real J_u and no partner; v in
+// {0, My/2} real vertical taps, whose conjugate outputs coincide with the
+// direct ones.
+template <int OP, int Q>
+__global__ __launch_bounds__(kWThreads) void k_ws_lsdft(StreamArgs a, LsdftTaps t)
+{
+    const int lid = xcd_local_id(blockIdx.x, gridDim.x);
+    const int job = lid % a.n_jobs, rest = lid / a.n_jobs;
+    const int mx = t.m[0], my = t.m[1], nu = mx / 2 + 1;
+    const int u = job % nu, v = job / nu;
+    const int mu = u == 0 ? 0 : mx - u, mv = v == 0 ? 0 : my - v;
+    FusedJob jb{};
+    jb.j_real = u == mu;
+    jb.c_real = v == mv;
+    jb.out_a = v * mx + u;
+    jb.out_b = jb.j_real ? -1 : v * mx + mu;
+    jb.out_c = jb.c_real ? -1 : mv * mx + mu;
+    jb.out_d = (jb.c_real || jb.j_real) ? -1 : mv * mx + u;
+    if (jb.j_real) ws_body<OP, Q, true, false, true>(a, jb, rest, &t, u, v);
+    else if (jb.c_real) ws_body<OP, Q, false, true, true>(a, jb, rest, &t, u, v);
+    else ws_body<OP, Q, false, false, true>(a, jb, rest, &t, u, v);
+}
+
 // Dynamic-LDS limits of the two kernels of one form and quarter (raised at
 // plan creation, so that no launch captured in a graph needs to).
 template <int OP, int Q>
@@ -528,6 +592,30 @@ hipError_t launch_ws_q(const StreamArgs& a, int n_blocks, hipStream_t stream)
     }
     hipLaunchKernelGGL((k_ws<OP, Q>), dim3(n_blocks), dim3(kWThreads), lds, stream, a);
     return hipGetLastError();
+}
+
+template <int OP, int Q>
+LdsLimit ws_lsdft_limit;
+
+template <int OP, int Q>
+hipError_t launch_ws_lsdft_q(const StreamArgs& a, const LsdftTaps& t, int n_blocks, hipStream_t stream)
+{
+    const size_t lds = WsShape<OP, Q>::lds_bytes;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    {
+        const hipError_t e = ws_lsdft_limit<OP, Q>.ensure((const void*)k_ws_lsdft<OP, Q>, lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_ws_lsdft<OP, Q>), dim3(n_blocks), dim3(kWThreads), lds, stream, a, t);
+    return hipGetLastError();
+}
+
+template <int OP, int... Qs>
+hipError_t launch_ws_lsdft_list(const StreamArgs& a, const LsdftTaps& t, int Q, int n_blocks, hipStream_t stream)
+{
+    hipError_t e = hipErrorInvalidValue;
+    ((Q == Qs ? (void)(e = launch_ws_lsdft_q<OP, Qs>(a, t, n_blocks, stream)) : (void)0), ...);
+    return e;
 }
 
 template <int OP, int Q>
@@ -584,6 +672,18 @@ hipError_t ws_prepare_form<GABOR_FORM>(int Q)
             return prepare_ws_list<GABOR_FORM, 8, 16, 24, 32, 40>(Q);
         else
             return prepare_ws_list<GABOR_FORM, 8, 16, 24, 32, 40, 48, 56>(Q);
+}
+
+// The localized SDFT uses windows of M <= 64 (R <= 32: Q <= 20 in FP32, 24
+// in the 16-bit forms).
+template <>
+hipError_t ws_lsdft_form<GABOR_FORM>(const StreamArgs& a, const LsdftTaps& t, int Q, int n_blocks,
+                                     hipStream_t stream)
+{
+    if constexpr (GABOR_FORM == FUSED_F32)
+        return launch_ws_lsdft_list<GABOR_FORM, 4, 8, 12, 16, 20>(a, t, Q, n_blocks, stream);
+    else
+        return launch_ws_lsdft_list<GABOR_FORM, 8, 16, 24>(a, t, Q, n_blocks, stream);
 }
 
 static LdsLimit ws_small_limit;
@@ -701,6 +801,24 @@ bool ws_supported(int op, int Q)
 {
     if (Q > ws_max_quarter(op)) return false;
     return op == FUSED_F32 ? Q % 4 == 0 : Q % 8 == 0;
+}
+
+hipError_t launch_ws_lsdft(int op, const StreamArgs& a, const LsdftTaps& t, int Q, hipStream_t stream)
+{
+    if (a.n_jobs <= 0) return hipSuccess;
+    if (!ws_supported(op, Q) || a.seg_rows <= 0 || a.seg_rows % 16 != 0 || 16 + 2 * a.R > 4 * Q)
+        return hipErrorInvalidValue;
+    if ((int64_t)a.H * a.W * 8 > (int64_t(1) << 30)) return hipErrorInvalidValue;
+    const long long nb = (long long)a.n_xs * a.n_ys * a.n_jobs;
+    if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    switch (op) {
+        case FUSED_F32: return ws_lsdft_form<FUSED_F32>(a, t, Q, (int)nb, stream);
+        case FUSED_BF16: return ws_lsdft_form<FUSED_BF16>(a, t, Q, (int)nb, stream);
+        case FUSED_BF16X3: return ws_lsdft_form<FUSED_BF16X3>(a, t, Q, (int)nb, stream);
+        case FUSED_F16: return ws_lsdft_form<FUSED_F16>(a, t, Q, (int)nb, stream);
+        case FUSED_F16X3: return ws_lsdft_form<FUSED_F16X3>(a, t, Q, (int)nb, stream);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_ws(int op, const StreamArgs& a, int Q, hipStream_t stream)
