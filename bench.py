@@ -437,6 +437,7 @@ def bench_layer(binding, workloads, steps, warmup):
     boundary; one forward and one backward (adjoint) of L = mean |F|^2."""
     import oracle
     import torch
+    from paper_1704_05231_amd import tuning
     from paper_1704_05231_amd.autograd import GaborLayer
     wl = workloads.bank_layer()
     x0 = torch.from_numpy(np.stack(wl.images)).cuda()
@@ -452,6 +453,9 @@ def bench_layer(binding, workloads, steps, warmup):
         (torch.linalg.vector_norm(torch.view_as_real(F)) ** 2 / F.numel()).backward()
         return x.grad
 
+    # segment heights tuned on the whole step (forward and adjoint over the
+    # batch); results do not depend on them
+    sched = tuning.tune_step(layer.bank, step)
     ms = event_time(step, steps, warmup)
     g = step().cpu().numpy()
     layer.bank.profile(True)
@@ -482,7 +486,7 @@ def bench_layer(binding, workloads, steps, warmup):
     return {"workload": wl.name, "ms_forward_backward": round(ms, 4), "value": n_out / (ms * 1e-3),
             "unit": "complex outputs/s (forward + backward)", "grad_max_rel_err_vs_oracle": err,
             "forward_launch_ms": fwd, "adjoint_ms": round(adj["total_ms"] / adj["launches"], 4) if adj else None,
-            "adjoint_roofline": adj_roof}
+            "adjoint_roofline": adj_roof, "schedule": sched}
 
 
 def bench_iir(binding, workloads, steps, warmup):

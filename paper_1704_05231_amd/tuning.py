@@ -106,3 +106,31 @@ def tune_batch(bank, images, reps: int = 3, mults=(1, 2, 4)) -> dict:
     bank.grouping = g
     return {"seg_rows": bank.tuning, "grouping": g,
             "candidates_ms": {f"grouping {gg}, x{mm}": round(t, 4) for (gg, mm), t in times.items()}}
+
+
+def tune_step(bank, step, reps: int = 5, mults=(1, 2, 4)) -> dict:
+    """Segment heights for a caller's whole step (for example a layer's
+    forward and adjoint over a batch): `step()` is timed with the bank's
+    current heights scaled by each of `mults` (capped at the plan height),
+    the median of `reps` timed calls after one warm-up, and the fastest
+    heights are applied.  Results do not depend on the choice.  Returns the
+    chosen heights and every candidate's time (ms)."""
+    import torch
+    base = bank.tuning
+    hmax = (bank.height + 15) // 16 * 16
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = {}
+    for m in mults:
+        bank.tuning = [min(s * m, hmax) if s else hmax for s in base]
+        step()
+        ts = []
+        for _ in range(reps):
+            start.record()
+            step()
+            stop.record()
+            stop.synchronize()
+            ts.append(start.elapsed_time(stop))
+        times[m] = sorted(ts)[len(ts) // 2]
+    m = min(times, key=times.get)
+    bank.tuning = [min(s * m, hmax) if s else hmax for s in base]
+    return {"seg_rows": bank.tuning, "candidates_ms": {f"x{mm}": round(t, 4) for mm, t in times.items()}}

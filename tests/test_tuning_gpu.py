@@ -137,3 +137,28 @@ def test_batch_tuner_keeps_results_bitwise(gpu_lib, prec):
         assert torch.equal(torch.view_as_real(a), torch.view_as_real(b))
     batch.close()
     bank.close()
+
+
+def test_step_tuner_keeps_layer_gradients_bitwise(gpu_lib):
+    """tuning.tune_step picks segment heights by timing a whole layer step
+    (forward and adjoint over a batch); the gradients keep every bit."""
+    import torch
+    from paper_1704_05231_amd import tuning
+    from paper_1704_05231_amd.autograd import GaborLayer
+    x0 = torch.from_numpy(np.stack([workloads.uniform_image(96, 112, 840 + i) for i in range(3)])).cuda()
+    layer = GaborLayer(96, 112, GROUP_OMEGAS, GROUP_SIGMAS, 8)
+
+    def step():
+        x = x0.detach().requires_grad_(True)
+        F = layer(x)
+        (torch.linalg.vector_norm(torch.view_as_real(F)) ** 2 / F.numel()).backward()
+        return x.grad
+
+    ref = step().clone()
+    sched = tuning.tune_step(layer.bank, step, reps=2)
+    print(f"layer schedule {sched}")
+    assert sched["seg_rows"] == layer.bank.tuning and len(sched["candidates_ms"]) == 3
+    got = step()
+    torch.cuda.synchronize()
+    assert torch.equal(ref, got)
+    layer.close()
