@@ -420,7 +420,7 @@ def bench_batch(binding, workloads, steps, warmup):
             worst = max(worst, float((np.abs(got - ref).max(0) / np.abs(ref).max(0)).max()))
         res["forms"][form] = {"ms": round(ms, 4), "value": n_out / (ms * 1e-3),
                               "ms_graph_replay": round(ms_graph, 4), "value_graph_replay": n_out / (ms_graph * 1e-3),
-                              "persistent_launches": n_launch, "tiles": n_tiles, "schedule": sched,
+                              "launches": n_launch, "tiles": n_tiles, "schedule": sched,
                               "max_rel_err_sampled": worst,
                               "roofline": hbm_roofline(nbytes, ms_graph, "whole batch per graph replay "
                                                                          "(one launch per operand size)")}

@@ -271,7 +271,7 @@ gabor_status gabor_batch_create(gabor_batch* out, gabor_plan plan, int32_t n_ima
                                 const int32_t* widths, const int64_t* row_strides,
                                 void* const* d_outs, void* hip_stream);
 gabor_status gabor_batch_apply(gabor_batch batch, void* hip_stream);
-/* Number of persistent launches and of tiles of a batch (either may be NULL). */
+/* Number of launches and of tiles of a batch (either may be NULL). */
 gabor_status gabor_batch_info(gabor_batch batch, int32_t* n_launches, int64_t* n_tiles);
 /* Release a batch's tile table.  NULL is accepted (no-op). */
 gabor_status gabor_batch_destroy(gabor_batch batch);

@@ -5,10 +5,10 @@
 //
 // Frequencies on the fused kernels are grouped by operand quarter Q; each
 // group is one launch over the tiles (image, job, strip segment) of every
-// image, in decreasing cost.  On the wave-specialised kernel tile b is
-// workgroup b, so the dispatcher hands out the longest tiles first and the
-// rest as workgroups free up; quarters beyond it run the persistent
-// four-wave kernel, each workgroup striding over the table.  One kernel
+// image, in decreasing cost.  Tile b is workgroup b (the wave-specialised
+// kernel, and beyond its quarters the four-wave one), so the dispatcher
+// hands out the longest tiles first and the rest as workgroups free up.
+// One kernel
 // over all quarters would carry the largest quarter's registers and LDS
 // into every tile (measured: 185 to 256 registers with spills against 124
 // to 177 per quarter), so each quarter keeps a launch of its own, except

@@ -522,17 +522,18 @@ __global__ __launch_bounds__(kThreads) void k_lsdft(StreamArgs a, LsdftTaps t)
     else stream_body<OP, Q, false, false, true>(a, jb, rest, &t, u, v);
 }
 
-// Persistent batch kernel: workgroup g takes tiles g, g + G, g + 2G, ...
-// (after the XCD remap, so neighbouring tiles, which share image strips,
-// stay on one XCD's L2).  The host orders tiles by decreasing length.
+// Batch kernel: workgroup b takes tile b of a table in dispatch order
+// (decreasing cost, equal-cost runs interleaved for the XCDs), as the
+// wave-specialised tile kernel does.  A persistent form (each workgroup
+// striding over the table) spilled 34-38 registers at Q = 56 in the split
+// forms, where the four-wave kernel already holds 256 + 235-248 per lane.
 template <int OP, int Q>
 __global__ __launch_bounds__(kThreads) void k_stream_batch(BatchArgs b)
 {
-    const int lid = xcd_local_id(blockIdx.x, gridDim.x);
-    for (int t = lid; t < b.n_tiles; t += gridDim.x) {
-        const BatchTile tl = b.tiles[t];
-        const BatchImage im = b.images[tl.image];
-        const BatchFreq fq = b.freqs[tl.freq];
+    {
+        const BatchTile tl = b.tiles[blockIdx.x];
+        const BatchImage& im = b.images[tl.image];
+        const BatchFreq& fq = b.freqs[tl.freq];
         StreamArgs a{};
         a.img = im.img;
         a.stride = im.stride;
@@ -551,7 +552,6 @@ __global__ __launch_bounds__(kThreads) void k_stream_batch(BatchArgs b)
         a.tap_scale[0] = fq.tap_scale[0];
         a.tap_scale[1] = fq.tap_scale[1];
         const FusedJob jb = b.jobs[tl.job];
-        lds_barrier();                                   // the previous tile is done with LDS
         if (jb.j_real) stream_body<OP, Q, true, false, false>(a, jb, tl.rest, nullptr, 0, 0);
         else if (jb.c_real) stream_body<OP, Q, false, true, false>(a, jb, tl.rest, nullptr, 0, 0);
         else stream_body<OP, Q, false, false, false>(a, jb, tl.rest, nullptr, 0, 0);
@@ -567,23 +567,8 @@ hipError_t launch_bq(const BatchArgs& b, hipStream_t stream)
         const hipError_t e = lim.ensure((const void*)k_stream_batch<OP, Q>, lds);
         if (e != hipSuccess) return e;
     }
-    // Resident capacity, found once per instantiation and device.
-    static int per_cu[64] = {0}, n_cu[64] = {0};
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
-    if (per_cu[dev] == 0) {
-        int blocks = 0, cus = 0;
-        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_stream_batch<OP, Q>, kThreads, lds)) != hipSuccess)
-            return e;
-        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-        n_cu[dev] = cus > 0 ? cus : 1;
-        per_cu[dev] = blocks > 0 ? blocks : 1;
-    }
-    const long long cap = (long long)per_cu[dev] * n_cu[dev];
-    const int grid = (int)(b.n_tiles < cap ? b.n_tiles : cap);
-    if (grid <= 0) return hipSuccess;
+    if (b.n_tiles <= 0) return hipSuccess;
+    const int grid = b.n_tiles;                         // one workgroup per tile
     hipLaunchKernelGGL((k_stream_batch<OP, Q>), dim3(grid), dim3(kThreads), lds, stream, b);
     return hipGetLastError();
 }

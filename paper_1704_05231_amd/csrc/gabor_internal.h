@@ -145,8 +145,8 @@ struct AdjFoldArgs {
 };
 hipError_t launch_adjoint_fold_sum(const AdjFoldArgs& a, hipStream_t stream);
 
-// Batched bank (one persistent launch per operand quarter): images of any
-// size up to the plan's, each tile one (image, job, strip segment).
+// Batched bank (one launch per operand quarter): images of any size up to
+// the plan's, each tile one (image, job, strip segment).
 struct BatchImage {
     const float* img;
     float2* out;               // [O][N][H][W] of this image
@@ -171,8 +171,8 @@ struct BatchArgs {
     const float* taps;
     int32_t n_tiles, boundary;
 };
-// Launches the persistent batch kernel of one form and quarter with as many
-// workgroups as fit on the device at once (at most n_tiles).
+// Launches the four-wave batch kernel of one form and quarter, one
+// workgroup per tile.
 hipError_t launch_batch(int op, const BatchArgs& b, int Q, hipStream_t stream);
 
 // Localized SDFT taps, passed by value as a kernel argument (no device

@@ -47,7 +47,7 @@ def test_batch_matches_single_image_and_oracle(gpu_lib, prec, boundary, monkeypa
     outs = [o.cpu().numpy() for o in batch()]
     torch.cuda.synchronize()
     n_launch, n_tiles = batch.info
-    # persistent fused launches and their tiles (none when every frequency
+    # fused launches and their tiles (none when every frequency
     # takes the two-pass kernels)
     assert (n_launch, n_tiles) == (0, 0) if twopass else (n_launch >= 1 and n_tiles > 0)
     thetas = workloads.orientations(N)
