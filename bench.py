@@ -61,6 +61,10 @@ SDFT_SOURCES = ["paper_1704_05231_amd/csrc/gabor_sdft.hip"]
 LSDFT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lsdft-512sq-16x16.json")
 LSDFT_SOURCES = ["paper_1704_05231_amd/csrc/gabor_ws.hip", "paper_1704_05231_amd/csrc/gabor_fused.hip",
                  "paper_1704_05231_amd/csrc/gabor_mfma.h", "paper_1704_05231_amd/csrc/gabor_lsdft.cpp"]
+# the same for one adjoint call of the layer workload (k_adj_stream per frequency, k_adj_sum)
+ADJ_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_layer-adjoint-32x512sq.json")
+ADJ_SOURCES = ["paper_1704_05231_amd/csrc/gabor_fused.hip", "paper_1704_05231_amd/csrc/gabor_mfma.h",
+               "paper_1704_05231_amd/csrc/gabor_plan.cpp"]
 IIR_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_iir-bank-1024sq-8x4-mirror.json")
 IIR_SOURCES = ["paper_1704_05231_amd/csrc/gabor_iir.hip"]
 
@@ -480,6 +484,15 @@ def bench_layer(binding, workloads, steps, warmup):
                     "launch_ms": round(avg, 5),
                     "kernel": (f"{adj_name}: k_adj_stream, one launch per frequency over the batch, and the sum"
                                if mfma else f"{adj_name}: vector-ALU row + column passes")}
+        # HBM bytes of the whole call from the counters under profiles/, while
+        # the kernel sources match the hash they were taken on
+        adj_tf = load_traffic(ADJ_TRAFFIC_FILE, ADJ_SOURCES) if mfma else None
+        if adj_tf and "adjoint" in adj_tf:
+            t = adj_tf["adjoint"]
+            adj_roof["traffic"] = t["hbm_bytes"]
+            adj_roof["traffic_detail"] = {"basis": "whole adjoint call", "fetch_bytes": t["fetch_bytes"],
+                                          "write_bytes": t["write_bytes"], "algorithmic_bytes": t["algorithmic_bytes"],
+                                          "ratio": t["ratio"]}
     layer.close()
     n_out = B * len(wl.omegas) * wl.n_orient * H * W
     fwd = {k: round(v["total_ms"] / v["launches"], 4) for k, v in prof.items() if not k.startswith("adjoint")}
