@@ -102,6 +102,19 @@ __device__ __forceinline__ void ws_body(const StreamArgs& a, const FusedJob& jb,
     // rounded once; the table sits in the J ring, which no pass uses before
     // every wave has read its bands.
     const float* tab = a.taps + jb.tap_off;
+    const float* tab_raw = tab;                    // unscaled, for the tap sums
+    // float16 forms: a copy of the table scaled for range (taps x 2^k, exact)
+    // staged in LDS, so that forming the band fragments takes no multiply
+    // (with it the Q = 40 split kernel spilled 67 registers to scratch, and
+    // every float16 kernel held 8-32 registers more)
+    constexpr bool PRESCALED = F::scaled && !LS;
+    if constexpr (PRESCALED) {
+        float* tl = reinterpret_cast<float*>(ws_lds4) + 16;      // past the prologue sums
+        for (int i = tid; i < 4 * KT; i += kWThreads)
+            tl[i] = tab[i] * (i < 2 * KT ? a.tap_scale[0] : a.tap_scale[1]);
+        lds_barrier();                                             // B0 (this form only)
+        tab = tl;
+    }
     if constexpr (LS) {
         float* tl = reinterpret_cast<float*>(ws_lds4) + 16;      // past the prologue sums
         for (int i = tid; i < 4 * KT; i += kWThreads) {
@@ -117,6 +130,7 @@ __device__ __forceinline__ void ws_body(const StreamArgs& a, const FusedJob& jb,
         }
         lds_barrier();                                             // B0 (this job kind only)
         tab = tl;
+        tab_raw = tl;
     }
     const float in_s = F::scaled ? a.in_scale : 1.0f, mid_s = F::scaled ? a.mid_scale : 1.0f;
     const float out_s = F::scaled ? a.out_scale : 1.0f;
@@ -133,8 +147,8 @@ __device__ __forceinline__ void ws_body(const StreamArgs& a, const FusedJob& jb,
 #pragma unroll
         for (int e = 0; e < Q; ++e) {
             const int m = 16 + Q * g + e - o;
-            xc[e] = sc(tab[row * KT + m], scale);
-            xd[e] = sc(tab[(row + 1) * KT + m], scale);
+            xc[e] = PRESCALED ? tab[row * KT + m] : sc(tab[row * KT + m], scale);
+            xd[e] = PRESCALED ? tab[(row + 1) * KT + m] : sc(tab[(row + 1) * KT + m], scale);
         }
         F::template pack<Q>(xc, ch, cl);
         F::template pack<Q>(xd, dh, dl);
@@ -145,7 +159,7 @@ __device__ __forceinline__ void ws_body(const StreamArgs& a, const FusedJob& jb,
         float v = 0.f;
         if (o == 0)
 #pragma unroll
-            for (int e = 0; e < Q; ++e) v += tab[row * KT + 16 + Q * g + e];
+            for (int e = 0; e < Q; ++e) v += tab_raw[row * KT + 16 + Q * g + e];
         v += __shfl_xor(v, 16);
         v += __shfl_xor(v, 32);
         return __shfl(v, 0);

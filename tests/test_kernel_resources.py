@@ -9,11 +9,8 @@ concurrently; each workgroup puts two waves on every SIMD, and a SIMD lane
 has 512 registers, VGPRs and AGPRs together).  A change that copies a larger
 struct into a kernel's locals, or keeps more values live, breaks them
 silently: a persistent form of the four-wave batch kernel spilled 34-38
-registers at Q = 56 and ran the frequency 16 % slower.
-
-One exception is measured and kept: the wave-specialised FP16 hi/lo kernel at
-Q = 40 (R 57 ... 72) spills to scratch, yet a 1024^2 apply at R = 60 takes
-65 us there against 83 us on the four-wave kernel, which does not spill."""
+registers at Q = 56 and ran the frequency 16 % slower, and forming the
+float16 band fragments with a range multiply spilled 67 at Q = 40."""
 import os
 import re
 import shutil
@@ -28,8 +25,6 @@ FORMS = range(5)
 # (source, form) pairs: the per-form objects and the form-independent ones
 UNITS = ([("gabor_ws.hip", f) for f in FORMS] + [("gabor_fused.hip", f) for f in FORMS]
          + [(s, 0) for s in ("gabor_fp32.hip", "gabor_adjoint.hip", "gabor_iir.hip", "gabor_sdft.hip")])
-# kernels allowed to use scratch (see the module docstring)
-SCRATCH_ALLOWED = {("gabor_ws.hip", 4): (r"k_wsILi4ELi40EE", r"k_ws_tilesILi4ELi40EE")}
 REGS_PER_SIMD_LANE = 512
 GRANULE = 8                     # register allocation granularity
 
@@ -88,18 +83,9 @@ def test_no_scratch(resources):
     for unit, res in resources.items():
         kernels = [k for k in res if "_ZN5gabor" in k and "k_" in k]
         assert kernels, (unit, sorted(res))
-        allowed = SCRATCH_ALLOWED.get(unit, ())
         for k in kernels:
-            r = res[k]
-            if any(re.search(a, k) for a in allowed):
-                continue
             # (register spills into AGPRs or VGPR lanes need no scratch and are allowed)
-            assert r.get("ScratchSize [bytes/lane]", 0) == 0, (unit, k, r)
-    # the exception is still there (when it goes, drop it from the list)
-    for unit, pats in SCRATCH_ALLOWED.items():
-        for a in pats:
-            hits = [k for k in resources[unit] if re.search(a, k)]
-            assert hits and all(resources[unit][k].get("ScratchSize [bytes/lane]", 0) > 0 for k in hits), (unit, a)
+            assert res[k].get("ScratchSize [bytes/lane]", 0) == 0, (unit, k, res[k])
 
 
 def test_fp32_r48_and_small_launch_share_a_compute_unit(resources):
